@@ -1,0 +1,159 @@
+"""X-stage benchmark on one MI355X.
+
+Workload: LWA-scale array, 256 antennas x 2 polarisations = 512 inputs,
+4096 channels, 4096 samples per integration, 4+4-bit complex samples
+(Gaussian noise plus a 5%-correlated point source with per-antenna delays),
+generated on the device from a fixed seed.
+
+One step = one integration window through the whole hot path: every sample of
+every channel read from HBM, unpacked, cross-multiplied on the int8 MFMA and
+integrated, and the exact int64 lower-triangle visibilities of all channels
+written to HBM (xcorr_accumulate_dump with reset).  Inputs are resident in HBM
+before the timed region.  The fp16-MFMA and plain fp32 kernels run the same
+window for comparison, and the CPU oracle is timed on a bounded sample.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "X-engine TCMAC/s and % int8-MFMA peak vs FP32 kernel, N=256 dual-pol"
+PEAK_INT8_TOPS = 5000.0       # MI355X dense int8 MFMA, vendor figure
+PEAK_FP16_TFLOPS = 2500.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_path(torch, xcorr, x, w, path, steps, warmup):
+    """Average ms of one accumulate_dump window on the plan's stream (HIP events)."""
+    p = xcorr.Plan(w.n_inputs, w.n_channels, w.fmt, path)
+    out = p.new_output()
+    for _ in range(warmup):
+        p.accumulate_dump(x, out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(p.stream)
+    for _ in range(steps):
+        p.accumulate_dump(x, out)
+    e1.record(p.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    info = p.query()
+    p.close()
+    return ms, out, info
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The oracle on a bounded sample of the same workload (host cores)."""
+    import oracle
+    from paper_1401_8288_amd import synth
+    threads = oracle.threads()
+    sample = synth.scaled(w, n_channels=threads)
+    x = synth.generate(sample, device="cpu").numpy()
+    t0 = time.perf_counter()
+    oracle.correlate(x, w.fmt)
+    t1 = time.perf_counter() - t0
+    reps = max(1, min(64, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.correlate(x, w.fmt)
+    dt = time.perf_counter() - t0
+    cmac = sample.cmac * reps
+    return {"value": round(cmac / dt / 1e12, 6), "unit": "TCMAC/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d passes over %d channels x %d inputs x %d samples (%.3g CMAC, %.1f s)"
+                      % (reps, sample.n_channels, w.n_inputs, w.n_time, cmac, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-compare", action="store_true", help="skip the fp16 / fp32 kernels")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the X-stage shards by channel with no exchange, "
+              "so there is no multi-GPU run here (got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1401_8288_amd import synth, xcorr
+
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS["lwa"]
+    log("generating", w.name, w.n_inputs, "inputs x", w.n_channels, "channels x", w.n_time, "samples")
+    x = synth.generate(w, device=dev)
+    torch.cuda.synchronize()
+
+    log("int8 MFMA path: %d warmup + %d timed windows" % (args.warmup, args.steps))
+    ms, out, info = time_path(torch, xcorr, x, w, "i8", args.steps, args.warmup)
+    cmac = w.cmac
+    tcmac = cmac / (ms * 1e-3) / 1e12
+    tops = 8 * cmac / (ms * 1e-3) / 1e12
+    hbm_bytes = w.input_bytes + w.output_bytes
+    log("int8: %.3f ms/window, %.1f TCMAC/s, %.1f%% of int8 peak" % (ms, tcmac, 100 * tops / PEAK_INT8_TOPS))
+
+    result = {
+        "metric": METRIC, "value": round(tcmac, 3), "unit": "TCMAC/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int8", "data": "synthetic (seeded, generated on device)",
+        "config": {"workload": "lwa: 256 antennas x 2 pol = 512 inputs, 4096 channels, "
+                               "4096 samples/integration, 4+4-bit complex",
+                   "n_inputs": w.n_inputs, "n_channels": w.n_channels, "n_time": w.n_time,
+                   "format": w.fmt, "path": "int8 MFMA, int32 partials, int64 output",
+                   "entry_point": "xcorr_accumulate_dump(reset=1)",
+                   "work_items": info.work_items},
+        "roofline": {"bound": "mfma", "kernel": "xcorr_i8_kernel<CI4>",
+                     "achieved": round(tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
+                     "frac": round(tops / PEAK_INT8_TOPS, 4), "traffic": None,
+                     "algorithmic_ops_per_launch": 8 * cmac,
+                     "algorithmic_bytes_per_launch": hbm_bytes,
+                     "hbm_gbs_algorithmic": round(hbm_bytes / (ms * 1e-3) / 1e9, 1)},
+        "pct_int8_peak": round(100 * tops / PEAK_INT8_TOPS, 2),
+    }
+    del out
+    torch.cuda.empty_cache()
+
+    if not args.no_compare:
+        comp = {}
+        for path, steps, peak, unit in (("f16", max(2, args.steps // 4), PEAK_FP16_TFLOPS, "TFLOP/s"),
+                                        ("f32", 2, PEAK_FP32_TFLOPS, "TFLOP/s")):
+            log("%s path: 1 warmup + %d timed windows" % (path, steps))
+            pms, pout, _ = time_path(torch, xcorr, x, w, path, steps, 1)
+            del pout
+            ptc = cmac / (pms * 1e-3) / 1e12
+            comp[path] = {"ms_per_step": round(pms, 3), "tcmac_s": round(ptc, 3),
+                          "achieved": round(8 * cmac / (pms * 1e-3) / 1e12, 2), "peak": peak,
+                          "unit": unit, "frac": round(8 * cmac / (pms * 1e-3) / 1e12 / peak, 4)}
+            log("%s: %.3f ms/window, %.2f TCMAC/s" % (path, pms, ptc))
+        comp["speedup_int8_vs_fp32"] = round(comp["f32"]["ms_per_step"] / ms, 2)
+        comp["speedup_int8_vs_fp16"] = round(comp["f16"]["ms_per_step"] / ms, 2)
+        result["compare"] = comp
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(w)
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

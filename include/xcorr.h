@@ -1,0 +1,138 @@
+/*
+ * xcorr.h -- C ABI of the MI355X (gfx950) X-stage library, libxcorr.so.
+ *
+ * The X-stage of an FX correlator (Sec. 1, Sec. 2.4 of Kocz et al., "A
+ * Scalable Hybrid FPGA/GPU FX Correlator"): for every frequency channel c,
+ * accumulate over an integration window the outer product of the vector of
+ * channelised voltages of all inputs with its own conjugate,
+ *
+ *     V[c][i][j] = sum_t  x_i[c,t] * conj(x_j[c,t]),        0 <= j <= i < N_i,
+ *
+ * i.e. the lower triangle of x x^H including the autocorrelations (Sec. 2.4,
+ * output-size equation), integrated on the GPU before it returns to the host
+ * (Sec. 2.1, Sec. 4).  Inputs are twice the number of antennas, one per
+ * polarisation (Sec. 2.2): input index i = 2 * antenna + pol.
+ *
+ * Data layout (all device memory, caller-owned, contiguous):
+ *   input   [n_channels][n_time][n_inputs] samples
+ *           XCORR_CI4: 1 byte per sample; high nibble = real part, low nibble =
+ *                      imaginary part, both two's-complement 4-bit integers in
+ *                      [-8, 7] (the 4+4-bit samples of Sec. 2.3).
+ *           XCORR_CI8: 2 bytes per sample, int8 real then int8 imaginary (the
+ *                      8-bit form of Sec. 2.4), full range [-128, 127].
+ *   output  [n_channels][n_inputs*(n_inputs+1)/2][2], entry (i, j) at packed
+ *           index i*(i+1)/2 + j, pair = (re, im).
+ *           XCORR_PATH_I8_MFMA: int64 (exact sums).
+ *           XCORR_PATH_F16_MFMA, XCORR_PATH_F32: float (fp32 accumulation).
+ * The dump returns sums; the paper's time average is sum / samples_accumulated.
+ *
+ * Ownership and ordering: a plan owns its device accumulators until
+ * xcorr_destroy.  Every call is enqueued on the plan's stream and returns
+ * without waiting (except where noted); the caller must keep `d_in` unchanged
+ * until the stream has passed the call, and `d_out` is valid once the stream
+ * has passed the dump.  A plan is not thread-safe; distinct plans may be used
+ * from distinct threads.
+ *
+ * Errors: every entry point returns an xcorr_status.  On any error nothing is
+ * enqueued and the plan is unchanged; xcorr_last_error() gives a message
+ * (thread-local).  No entry point throws or aborts.
+ */
+#ifndef XCORR_H
+#define XCORR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    XCORR_OK = 0,
+    XCORR_ERR_ARG = -1,          /* null/misaligned pointer, bad size or enum        */
+    XCORR_ERR_NOMEM = -2,        /* device allocation failed                          */
+    XCORR_ERR_DEVICE = -3,       /* HIP runtime error (see xcorr_last_error)          */
+    XCORR_ERR_STATE = -4,        /* plan handle not valid                             */
+    XCORR_ERR_UNSUPPORTED = -6   /* device is not gfx950, or shape not supported      */
+} xcorr_status;
+
+typedef enum { XCORR_CI4 = 0, XCORR_CI8 = 1 } xcorr_format;
+
+typedef enum {
+    XCORR_PATH_I8_MFMA = 0,      /* int8 MFMA, int32 partials, int64 output: exact    */
+    XCORR_PATH_F16_MFMA = 1,     /* fp16 MFMA, fp32 accumulation, float output         */
+    XCORR_PATH_F32 = 2           /* plain fp32 vector kernel, float output             */
+} xcorr_path;
+
+/* Plan flags. */
+#define XCORR_FLAG_NO_XCD_MAP 0x2u /* dispatch work items in plain order (for tests)  */
+
+typedef struct xcorr_plan_s* xcorr_plan_t;
+
+typedef struct {
+    int32_t n_inputs;            /* N_i >= 1, multiple of 4 (CI4) or 2 (CI8)          */
+    int32_t n_channels;          /* N_c >= 1                                          */
+    int32_t format;              /* xcorr_format                                      */
+    int32_t path;                /* xcorr_path                                        */
+    void* stream;                /* hipStream_t, NULL = the null stream               */
+    uint32_t flags;              /* XCORR_FLAG_*                                      */
+    int32_t tile;                /* 0 = tuned default; else a tile variant id         */
+} xcorr_plan_desc;
+
+typedef struct {
+    int64_t samples_accumulated; /* samples summed into the dumped result            */
+    int64_t start_sample;        /* running sample index at which this window began  */
+    int64_t n_dumps;             /* dumps taken from this plan so far (incl. this)   */
+} xcorr_dump_info;
+
+typedef struct {
+    size_t device_bytes;         /* device memory the plan holds                      */
+    size_t output_bytes;         /* bytes of one dump                                 */
+    size_t input_bytes_per_sample; /* bytes of one time sample of all channels       */
+    int64_t fold_bound;          /* max samples per kernel launch (int32 partials)    */
+    int32_t tile;                /* tile variant in use                               */
+    int32_t work_items;          /* workgroups per launch (one time chunk)            */
+    int32_t items_per_group;     /* workgroups per channel group                      */
+    int32_t channels_per_group;  /* channels sharing one set of work items            */
+} xcorr_plan_info;
+
+/* Create a plan: validates the descriptor, checks the device is gfx950 and
+ * allocates the plan's accumulators on the current device.  *out is set only
+ * on success. */
+xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* desc);
+
+/* Add n_time samples of every channel of d_in to the plan's accumulators.
+ * d_in: device pointer, layout above, 16-byte aligned.  n_time == 0 is a
+ * no-op.  Windows longer than fold_bound are split into several launches. */
+xcorr_status xcorr_accumulate(xcorr_plan_t plan, const void* d_in, int64_t n_time);
+
+/* Write the accumulated visibilities to d_out (device, layout above, 16-byte
+ * aligned).  reset != 0 restarts the integration.  info may be NULL. */
+xcorr_status xcorr_dump(xcorr_plan_t plan, void* d_out, int reset, xcorr_dump_info* info);
+
+/* xcorr_accumulate followed by xcorr_dump, fused: the last launch writes the
+ * result straight to d_out, so a window that starts from a reset plan costs
+ * one read of the input and one write of the output. */
+xcorr_status xcorr_accumulate_dump(xcorr_plan_t plan, const void* d_in, int64_t n_time,
+                                   void* d_out, int reset, xcorr_dump_info* info);
+
+/* Sizes and the work decomposition chosen for the plan. */
+xcorr_status xcorr_query(xcorr_plan_t plan, xcorr_plan_info* info);
+
+/* Bytes of device memory a plan with this descriptor would hold (admission
+ * control); no allocation. */
+xcorr_status xcorr_plan_bytes(const xcorr_plan_desc* desc, size_t* bytes);
+
+/* Release the plan (waits for its stream).  Destroying NULL is XCORR_ERR_STATE. */
+xcorr_status xcorr_destroy(xcorr_plan_t plan);
+
+const char* xcorr_strerror(xcorr_status status);
+const char* xcorr_last_error(void);
+
+/* Library version, 10000 * major + 100 * minor + patch. */
+int32_t xcorr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XCORR_H */

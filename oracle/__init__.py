@@ -59,6 +59,9 @@ def lib():
         L.xo_correlate.argtypes = [ctypes.c_void_p, ctypes.c_int, i64, i64, i64, i64, i64,
                                    ctypes.c_void_p]
         L.xo_correlate.restype = ctypes.c_int
+        L.xo_correlate_rows.argtypes = [ctypes.c_void_p, ctypes.c_int, i64, i64, i64, i64, i64,
+                                        i64, ctypes.c_void_p]
+        L.xo_correlate_rows.restype = ctypes.c_int
         L.xo_beam_power.argtypes = [ctypes.c_void_p, ctypes.c_int, i64, i64, i64,
                                     ctypes.c_void_p, ctypes.c_void_p]
         L.xo_beam_power.restype = ctypes.c_int
@@ -101,6 +104,24 @@ def correlate(x: np.ndarray, fmt: str, channels=None) -> np.ndarray:
     out = np.empty((count, n_baselines(n_in), 2), dtype=np.int64)
     rc = lib().xo_correlate(x.ctypes.data, FORMATS[fmt], n_ch, n_t, n_in, begin, count,
                             out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return out
+
+
+def correlate_rows(x: np.ndarray, fmt: str, channel: int, row_begin: int, row_count: int):
+    """Rows [row_begin, row_begin+row_count) of one channel's triangle.
+
+    Returns int64 [sum of (i+1) over the rows][2], the same entries in the same
+    order as the packed triangle of a full result.
+    """
+    n_ch, n_t, n_in = _shape(x, fmt)
+    x = np.ascontiguousarray(x)
+    r0, r1 = row_begin, row_begin + row_count
+    n = r1 * (r1 + 1) // 2 - r0 * (r0 + 1) // 2
+    out = np.empty((n, 2), dtype=np.int64)
+    rc = lib().xo_correlate_rows(x.ctypes.data, FORMATS[fmt], n_ch, n_t, n_in, channel, r0,
+                                 row_count, out.ctypes.data)
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return out

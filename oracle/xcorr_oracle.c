@@ -112,6 +112,42 @@ int xo_correlate(const void* in, int fmt, int64_t n_ch, int64_t n_t, int64_t n_i
 }
 
 /*
+ * Rows [row_begin, row_begin + row_count) of the triangle of one channel:
+ * out receives, row after row, the entries (i, 0..i) as (re, im) int64 pairs
+ * (sum over rows of (i + 1) pairs).  Same definition as xo_correlate, for
+ * checking a sample of a channel too large to correlate whole; the rows are
+ * shared out over the threads.  Returns 0, or -1 on a bad argument.
+ */
+int xo_correlate_rows(const void* in, int fmt, int64_t n_ch, int64_t n_t, int64_t n_in,
+                      int64_t ch, int64_t row_begin, int64_t row_count, int64_t* out)
+{
+    if (!in || !out || (fmt != 0 && fmt != 1) || n_t < 0 || n_in <= 0 || ch < 0 || ch >= n_ch ||
+        row_begin < 0 || row_count < 0 || row_begin + row_count > n_in)
+        return -1;
+    const int64_t bps = (fmt == 0) ? 1 : 2;
+    const uint8_t* base = (const uint8_t*)in;
+    /* first output pair of row i: sum_{r < i} (r + 1) - sum_{r < row_begin} (r + 1) */
+    const int64_t first = row_begin * (row_begin + 1) / 2;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = row_begin; i < row_begin + row_count; ++i) {
+        int64_t* acc = out + (i * (i + 1) / 2 - first) * 2;
+        memset(acc, 0, (size_t)(i + 1) * 2 * sizeof(int64_t));
+        for (int64_t t = 0; t < n_t; ++t) {
+            const uint8_t* row = base + (ch * n_t + t) * n_in * bps;
+            int64_t ar, ai;
+            xo_decode(row, fmt, i, &ar, &ai);
+            for (int64_t j = 0; j <= i; ++j) {
+                int64_t br, bi;
+                xo_decode(row, fmt, j, &br, &bi);
+                acc[2 * j]     += ar * br + ai * bi;
+                acc[2 * j + 1] += ai * br - ar * bi;
+            }
+        }
+    }
+    return 0;
+}
+
+/*
  * Beamformed power of every channel: for the complex integer weights w
  * (n_in (re, im) pairs, shared by all channels),
  *

@@ -1,0 +1,419 @@
+// Host side of libxcorr: argument checking, plan state, work decomposition
+// and the launch sequence of accumulate / dump.  See include/xcorr.h.
+#include "xcorr.h"
+#include "xcorr_internal.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+using namespace xcorr;
+
+struct xcorr_plan_s {
+    xcorr_plan_desc d;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n_b = 0;                // baselines per channel
+    size_t out_bytes = 0;
+    void* acc = nullptr;            // accumulator, same layout as a dump
+    bool acc_valid = false;         // false: accumulator is logically zero
+    WorkItem* d_items = nullptr;
+    int n_items = 0;                // items per channel group
+    int ch_group = 1;
+    int n_groups = 0;
+    int xcd_map = 1;
+    int64_t fold_bound = 0;
+    int64_t samples = 0;            // samples since the last reset
+    int64_t window_start = 0;       // absolute sample index of the current window
+    int64_t total = 0;              // absolute samples accumulated
+    int64_t n_dumps = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+std::mutex g_mu;
+std::set<xcorr_plan_t> g_live;
+
+xcorr_status fail(xcorr_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+xcorr_status fail(xcorr_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+xcorr_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(XCORR_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void release(void* ptr)
+{
+    if (ptr) (void)hipFree(ptr);
+}
+
+bool live(xcorr_plan_t p)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return p != nullptr && g_live.count(p) != 0;
+}
+
+// Lower-triangle work items for W row blocks of 64 inputs.  Off-diagonal
+// pairs of row-block pairs become four FULL tiles; a diagonal pair becomes
+// two DIAG tiles plus the off-diagonal tile between them split in two halves,
+// so that no wave of the workgroup carries more than 10 of 16 blocks.
+void plan_items(int W, std::vector<WorkItem>& items, int& ch_group)
+{
+    items.clear();
+    auto blank = []() {
+        WorkItem it;
+        for (int k = 0; k < kSlots; ++k) { it.rb[k] = -1; it.ch[k] = 0; }
+        for (int w = 0; w < kWaves; ++w) { it.wi[w] = 0; it.wj[w] = 0; it.kind[w] = KIND_NONE; }
+        it.pad[0] = it.pad[1] = 0;
+        return it;
+    };
+    if (W == 1) {
+        // one row block per channel: four channels per workgroup, one DIAG tile each
+        ch_group = kWaves;
+        WorkItem it = blank();
+        for (int w = 0; w < kWaves; ++w) {
+            it.rb[w] = 0;
+            it.ch[w] = (int8_t)w;
+            it.wi[w] = it.wj[w] = (int8_t)w;
+            it.kind[w] = KIND_DIAG;
+        }
+        items.push_back(it);
+        return;
+    }
+    ch_group = 1;
+    const int SB = (W + 1) / 2;
+    for (int R = 0; R < SB; ++R) {
+        int rr[2], nr = 0;
+        for (int k = 0; k < 2; ++k) if (2 * R + k < W) rr[nr++] = 2 * R + k;
+        for (int S = 0; S <= R; ++S) {
+            WorkItem it = blank();
+            if (S < R) {
+                int ss[2], ns = 0;
+                for (int k = 0; k < 2; ++k) if (2 * S + k < W) ss[ns++] = 2 * S + k;
+                int slot = 0;
+                for (int k = 0; k < nr; ++k) it.rb[slot++] = (int16_t)rr[k];
+                for (int k = 0; k < ns; ++k) it.rb[slot++] = (int16_t)ss[k];
+                int w = 0;
+                for (int a = 0; a < nr; ++a)
+                    for (int b = 0; b < ns; ++b) {
+                        it.wi[w] = (int8_t)a;
+                        it.wj[w] = (int8_t)(nr + b);
+                        it.kind[w] = KIND_FULL;
+                        ++w;
+                    }
+            } else if (nr == 2) {
+                it.rb[0] = (int16_t)rr[0];
+                it.rb[1] = (int16_t)rr[1];
+                it.wi[0] = 1; it.wj[0] = 0; it.kind[0] = KIND_HALF0;
+                it.wi[1] = 1; it.wj[1] = 0; it.kind[1] = KIND_HALF1;
+                it.wi[2] = 0; it.wj[2] = 0; it.kind[2] = KIND_DIAG;
+                it.wi[3] = 1; it.wj[3] = 1; it.kind[3] = KIND_DIAG;
+            } else {
+                it.rb[0] = (int16_t)rr[0];
+                it.wi[0] = 0; it.wj[0] = 0; it.kind[0] = KIND_DIAG;
+            }
+            items.push_back(it);
+        }
+    }
+}
+
+size_t elem_bytes(int path) { return path == XCORR_PATH_I8_MFMA ? 8 : 4; }
+
+xcorr_status check_desc(const xcorr_plan_desc* d)
+{
+    if (!d) return fail(XCORR_ERR_ARG, "null descriptor");
+    if (d->format != XCORR_CI4 && d->format != XCORR_CI8)
+        return fail(XCORR_ERR_ARG, "unknown format %d", d->format);
+    if (d->path != XCORR_PATH_I8_MFMA && d->path != XCORR_PATH_F16_MFMA && d->path != XCORR_PATH_F32)
+        return fail(XCORR_ERR_ARG, "unknown path %d", d->path);
+    if (d->n_inputs < 1 || d->n_channels < 1)
+        return fail(XCORR_ERR_ARG, "n_inputs and n_channels must be >= 1");
+    if (d->n_inputs > 32768)
+        return fail(XCORR_ERR_UNSUPPORTED, "n_inputs %d above 32768", d->n_inputs);
+    const int align = d->format == XCORR_CI4 ? 4 : 2;
+    if (d->n_inputs % align)
+        return fail(XCORR_ERR_UNSUPPORTED, "n_inputs must be a multiple of %d for this format",
+                    align);
+    if (d->flags & ~XCORR_FLAG_NO_XCD_MAP)
+        return fail(XCORR_ERR_ARG, "unknown flags 0x%x", d->flags);
+    if (d->tile != 0) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
+    return XCORR_OK;
+}
+
+size_t plan_device_bytes(const xcorr_plan_desc* d, size_t n_items)
+{
+    const int64_t n_b = (int64_t)d->n_inputs * (d->n_inputs + 1) / 2;
+    return (size_t)n_b * d->n_channels * 2 * elem_bytes(d->path) + n_items * sizeof(WorkItem) + 256;
+}
+
+xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
+                          const void* src, void* dst)
+{
+    LaunchArgs a;
+    a.in = in;
+    a.chan_stride = chan_stride;
+    a.row_bytes = p->d.n_inputs * (p->d.format == XCORR_CI4 ? 1 : 2);
+    a.n_inputs = p->d.n_inputs;
+    a.t_len = t_len;
+    a.n_channels = p->d.n_channels;
+    a.ch_group = p->ch_group;
+    a.n_items = p->n_items;
+    a.n_blocks = p->n_items * p->n_groups;
+    a.xcd_map = p->xcd_map;
+    a.items = p->d_items;
+    a.src = src;
+    a.dst = dst;
+    hipError_t e;
+    switch (p->d.path) {
+    case XCORR_PATH_I8_MFMA: e = launch_i8(a, p->d.format, p->stream); break;
+    case XCORR_PATH_F16_MFMA: e = launch_f16(a, p->d.format, p->stream); break;
+    default: e = launch_f32(a, p->d.format, p->stream); break;
+    }
+    if (e != hipSuccess) return hip_fail(e, "X-stage kernel launch");
+    return XCORR_OK;
+}
+
+xcorr_status check_ptr(const void* ptr, const char* name)
+{
+    if (!ptr) return fail(XCORR_ERR_ARG, "%s is null", name);
+    if ((uintptr_t)ptr % 16) return fail(XCORR_ERR_ARG, "%s is not 16-byte aligned", name);
+    return XCORR_OK;
+}
+
+// Runs the launches of one window.  If `final_dst` is non-null the last chunk
+// writes its result there instead of into the accumulator.
+xcorr_status run_window(xcorr_plan_t p, const void* d_in, int64_t n_time, void* final_dst)
+{
+    const int64_t row = (int64_t)p->d.n_inputs * (p->d.format == XCORR_CI4 ? 1 : 2);
+    const int64_t chan_stride = row * n_time;
+    const uint8_t* in = (const uint8_t*)d_in;
+    for (int64_t t0 = 0; t0 < n_time; t0 += p->fold_bound) {
+        const int64_t len = std::min<int64_t>(p->fold_bound, n_time - t0);
+        const bool last = t0 + len >= n_time;
+        void* dst = (last && final_dst) ? final_dst : p->acc;
+        const void* src = p->acc_valid ? p->acc : nullptr;
+        xcorr_status s = launch_chunk(p, in + t0 * row, chan_stride, (int32_t)len, src, dst);
+        if (s != XCORR_OK) return s;
+        if (dst == p->acc) p->acc_valid = true;
+    }
+    return XCORR_OK;
+}
+
+void fill_info(xcorr_plan_t p, xcorr_dump_info* info)
+{
+    if (!info) return;
+    info->samples_accumulated = p->samples;
+    info->start_sample = p->window_start;
+    info->n_dumps = p->n_dumps;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t xcorr_version(void) { return 100; }
+
+const char* xcorr_last_error(void) { return g_err.c_str(); }
+
+const char* xcorr_strerror(xcorr_status s)
+{
+    switch (s) {
+    case XCORR_OK: return "ok";
+    case XCORR_ERR_ARG: return "invalid argument";
+    case XCORR_ERR_NOMEM: return "out of device memory";
+    case XCORR_ERR_DEVICE: return "device (HIP) error";
+    case XCORR_ERR_STATE: return "invalid plan handle";
+    case XCORR_ERR_UNSUPPORTED: return "unsupported device or shape";
+    }
+    return "unknown status";
+}
+
+xcorr_status xcorr_plan_bytes(const xcorr_plan_desc* d, size_t* bytes)
+{
+    xcorr_status s = check_desc(d);
+    if (s != XCORR_OK) return s;
+    if (!bytes) return fail(XCORR_ERR_ARG, "null output");
+    std::vector<WorkItem> items;
+    int cg;
+    plan_items((d->n_inputs + kRowBlock - 1) / kRowBlock, items, cg);
+    *bytes = plan_device_bytes(d, items.size());
+    return XCORR_OK;
+}
+
+xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
+{
+    if (!out) return fail(XCORR_ERR_ARG, "null plan output");
+    xcorr_status s = check_desc(d);
+    if (s != XCORR_OK) return s;
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(XCORR_ERR_UNSUPPORTED, "device %d is %s, not gfx950", dev, prop.gcnArchName);
+
+    xcorr_plan_t p = new (std::nothrow) xcorr_plan_s();
+    if (!p) return fail(XCORR_ERR_NOMEM, "host allocation");
+    p->d = *d;
+    p->device = dev;
+    p->stream = (hipStream_t)d->stream;
+    p->n_b = (int64_t)d->n_inputs * (d->n_inputs + 1) / 2;
+    p->out_bytes = (size_t)p->n_b * d->n_channels * 2 * elem_bytes(d->path);
+    p->xcd_map = (d->flags & XCORR_FLAG_NO_XCD_MAP) ? 0 : 1;
+    // int8 path: int32 partial sums are exact for 65535 samples; fp paths
+    // accumulate in fp32 without a count limit.
+    p->fold_bound = d->path == XCORR_PATH_I8_MFMA ? 65535 : (int64_t)1 << 30;
+    // one launch's samples of one channel must stay below 2^31 bytes (the
+    // kernels address a channel through a 32-bit buffer range)
+    const int64_t row = (int64_t)d->n_inputs * (d->format == XCORR_CI4 ? 1 : 2);
+    p->fold_bound = std::min<int64_t>(p->fold_bound, ((int64_t)1 << 31) / row - 1);
+
+    std::vector<WorkItem> items;
+    plan_items((d->n_inputs + kRowBlock - 1) / kRowBlock, items, p->ch_group);
+    p->n_items = (int)items.size();
+    p->n_groups = (d->n_channels + p->ch_group - 1) / p->ch_group;
+    const int64_t blocks = (int64_t)p->n_items * p->n_groups;
+    if (blocks > (int64_t)1 << 30) {
+        delete p;
+        return fail(XCORR_ERR_UNSUPPORTED, "too many work items");
+    }
+
+    e = hipMalloc(&p->acc, p->out_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, items.size() * sizeof(WorkItem));
+    if (e != hipSuccess) {
+        release(p->acc);
+        release(p->d_items);
+        delete p;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? XCORR_ERR_NOMEM : XCORR_ERR_DEVICE,
+                    "plan allocation: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        release(p->acc);
+        release(p->d_items);
+        delete p;
+        return hip_fail(e, "work item upload");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.insert(p);
+    }
+    *out = p;
+    return XCORR_OK;
+}
+
+xcorr_status xcorr_accumulate(xcorr_plan_t p, const void* d_in, int64_t n_time)
+{
+    if (!live(p)) return fail(XCORR_ERR_STATE, "invalid plan handle");
+    if (n_time < 0) return fail(XCORR_ERR_ARG, "negative n_time");
+    if (n_time == 0) return XCORR_OK;
+    xcorr_status s = check_ptr(d_in, "d_in");
+    if (s != XCORR_OK) return s;
+    s = run_window(p, d_in, n_time, nullptr);
+    if (s != XCORR_OK) return s;
+    p->samples += n_time;
+    p->total += n_time;
+    return XCORR_OK;
+}
+
+xcorr_status xcorr_dump(xcorr_plan_t p, void* d_out, int reset, xcorr_dump_info* info)
+{
+    if (!live(p)) return fail(XCORR_ERR_STATE, "invalid plan handle");
+    xcorr_status s = check_ptr(d_out, "d_out");
+    if (s != XCORR_OK) return s;
+    hipError_t e = p->acc_valid ? launch_copy(d_out, p->acc, p->out_bytes, p->stream)
+                                : launch_fill_zero(d_out, p->out_bytes, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "dump");
+    p->n_dumps += 1;
+    fill_info(p, info);
+    if (reset) {
+        p->acc_valid = false;
+        p->samples = 0;
+        p->window_start = p->total;
+    }
+    return XCORR_OK;
+}
+
+xcorr_status xcorr_accumulate_dump(xcorr_plan_t p, const void* d_in, int64_t n_time, void* d_out,
+                                   int reset, xcorr_dump_info* info)
+{
+    if (!live(p)) return fail(XCORR_ERR_STATE, "invalid plan handle");
+    if (n_time < 0) return fail(XCORR_ERR_ARG, "negative n_time");
+    xcorr_status s = check_ptr(d_out, "d_out");
+    if (s != XCORR_OK) return s;
+    if (n_time == 0) return xcorr_dump(p, d_out, reset, info);
+    s = check_ptr(d_in, "d_in");
+    if (s != XCORR_OK) return s;
+    if (reset) {
+        // the last launch writes the dump directly; the accumulator restarts
+        s = run_window(p, d_in, n_time, d_out);
+        if (s != XCORR_OK) return s;
+        p->acc_valid = false;
+    } else {
+        s = run_window(p, d_in, n_time, nullptr);
+        if (s != XCORR_OK) return s;
+        hipError_t e = launch_copy(d_out, p->acc, p->out_bytes, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "dump copy");
+    }
+    p->samples += n_time;
+    p->total += n_time;
+    p->n_dumps += 1;
+    fill_info(p, info);
+    if (reset) {
+        p->samples = 0;
+        p->window_start = p->total;
+    }
+    return XCORR_OK;
+}
+
+xcorr_status xcorr_query(xcorr_plan_t p, xcorr_plan_info* info)
+{
+    if (!live(p)) return fail(XCORR_ERR_STATE, "invalid plan handle");
+    if (!info) return fail(XCORR_ERR_ARG, "null info");
+    info->device_bytes = plan_device_bytes(&p->d, p->n_items);
+    info->output_bytes = p->out_bytes;
+    info->input_bytes_per_sample =
+        (size_t)p->d.n_inputs * (p->d.format == XCORR_CI4 ? 1 : 2) * p->d.n_channels;
+    info->fold_bound = p->fold_bound;
+    info->tile = 0;
+    info->work_items = p->n_items * p->n_groups;
+    info->items_per_group = p->n_items;
+    info->channels_per_group = p->ch_group;
+    return XCORR_OK;
+}
+
+xcorr_status xcorr_destroy(xcorr_plan_t p)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (p == nullptr || g_live.erase(p) == 0) return fail(XCORR_ERR_STATE, "invalid plan handle");
+    }
+    hipError_t e = hipStreamSynchronize(p->stream);
+    release(p->acc);
+    release(p->d_items);
+    delete p;
+    if (e != hipSuccess) return hip_fail(e, "destroy: stream synchronize");
+    return XCORR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+"""Python binding of libxcorr (include/xcorr.h): argument marshalling only.
+
+Every step of the X-stage runs in the HIP library; this module checks tensor
+shapes, passes device pointers and the current torch stream across the C ABI
+and turns status codes into exceptions.  torch is imported first so that the
+library binds to the HIP runtime torch has already loaded.  There is no
+fallback: if the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxcorr.so")
+
+CI4, CI8 = 0, 1
+PATH_I8, PATH_F16, PATH_F32 = 0, 1, 2
+FLAG_NO_XCD_MAP = 0x2
+
+FORMATS = {"ci4": CI4, "ci8": CI8}
+PATHS = {"i8": PATH_I8, "f16": PATH_F16, "f32": PATH_F32}
+
+EXPORTS = ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dump",
+           "xcorr_query", "xcorr_plan_bytes", "xcorr_destroy", "xcorr_strerror",
+           "xcorr_last_error", "xcorr_version")
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("n_inputs", ctypes.c_int32), ("n_channels", ctypes.c_int32),
+                ("format", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("flags", ctypes.c_uint32),
+                ("tile", ctypes.c_int32)]
+
+
+class DumpInfo(ctypes.Structure):
+    _fields_ = [("samples_accumulated", ctypes.c_int64), ("start_sample", ctypes.c_int64),
+                ("n_dumps", ctypes.c_int64)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_size_t), ("output_bytes", ctypes.c_size_t),
+                ("input_bytes_per_sample", ctypes.c_size_t), ("fold_bound", ctypes.c_int64),
+                ("tile", ctypes.c_int32), ("work_items", ctypes.c_int32),
+                ("items_per_group", ctypes.c_int32), ("channels_per_group", ctypes.c_int32)]
+
+
+class XcorrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("xcorr status %d: %s" % (status, message))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libxcorr.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_1401_8288_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.xcorr_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc)]
+    L.xcorr_accumulate.argtypes = [vp, vp, i64]
+    L.xcorr_dump.argtypes = [vp, vp, i32, ctypes.POINTER(DumpInfo)]
+    L.xcorr_accumulate_dump.argtypes = [vp, vp, i64, vp, i32, ctypes.POINTER(DumpInfo)]
+    L.xcorr_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    L.xcorr_plan_bytes.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_size_t)]
+    L.xcorr_destroy.argtypes = [vp]
+    L.xcorr_strerror.argtypes = [i32]
+    L.xcorr_strerror.restype = ctypes.c_char_p
+    L.xcorr_last_error.restype = ctypes.c_char_p
+    L.xcorr_version.restype = ctypes.c_int32
+    for name in ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dump",
+                 "xcorr_query", "xcorr_plan_bytes", "xcorr_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != 0:
+        raise XcorrError(status, lib.xcorr_last_error().decode())
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def make_desc(n_inputs, n_channels, fmt="ci4", path="i8", stream=None, flags=0, tile=0,
+              stream_ptr: int | None = None) -> PlanDesc:
+    sp = stream_ptr if stream_ptr is not None else (
+        int(stream.cuda_stream) if stream is not None else 0)
+    return PlanDesc(int(n_inputs), int(n_channels), FORMATS[fmt], PATHS[path],
+                    ctypes.c_void_p(sp), int(flags), int(tile))
+
+
+def plan_bytes(n_inputs, n_channels, fmt="ci4", path="i8") -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib.xcorr_plan_bytes(ctypes.byref(make_desc(n_inputs, n_channels, fmt, path)),
+                                ctypes.byref(out)))
+    return int(out.value)
+
+
+@dataclass
+class Dump:
+    samples_accumulated: int
+    start_sample: int
+    n_dumps: int
+
+
+class Plan:
+    """One X-stage plan: device accumulators for n_channels x n_inputs.
+
+    Calls are enqueued on `stream` (default: torch's current stream at plan
+    creation) and return without waiting.
+    """
+
+    def __init__(self, n_inputs: int, n_channels: int, fmt: str = "ci4", path: str = "i8",
+                 stream: torch.cuda.Stream | None = None, flags: int = 0, tile: int = 0):
+        self.n_inputs, self.n_channels, self.fmt, self.path = n_inputs, n_channels, fmt, path
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = self.stream.device
+        desc = make_desc(n_inputs, n_channels, fmt, path, self.stream, flags, tile)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.xcorr_plan(ctypes.byref(h), ctypes.byref(desc)))
+        self._h = h
+        self.n_baselines = n_inputs * (n_inputs + 1) // 2
+
+    # ---------------------------------------------------------------- helpers
+    @property
+    def out_dtype(self):
+        return torch.int64 if self.path == "i8" else torch.float32
+
+    def out_shape(self):
+        return (self.n_channels, self.n_baselines, 2)
+
+    def new_output(self) -> torch.Tensor:
+        return torch.empty(self.out_shape(), dtype=self.out_dtype, device=self.device)
+
+    def _check_input(self, x: torch.Tensor) -> int:
+        if not isinstance(x, torch.Tensor) or x.device != self.device:
+            raise ValueError("input must be a tensor on %s" % self.device)
+        if not x.is_contiguous():
+            raise ValueError("input must be contiguous")
+        if self.fmt == "ci4":
+            if x.dtype != torch.uint8 or x.dim() != 3:
+                raise ValueError("ci4 input must be uint8 [channel][time][input]")
+            c, t, n = x.shape
+        else:
+            if x.dtype != torch.int8 or x.dim() != 4 or x.shape[3] != 2:
+                raise ValueError("ci8 input must be int8 [channel][time][input][2]")
+            c, t, n, _ = x.shape
+        if c != self.n_channels or n != self.n_inputs:
+            raise ValueError("input shape %s does not match the plan" % (tuple(x.shape),))
+        return t
+
+    def _check_output(self, out: torch.Tensor):
+        if (out.device != self.device or out.dtype != self.out_dtype or
+                tuple(out.shape) != self.out_shape() or not out.is_contiguous()):
+            raise ValueError("output must be a contiguous %s tensor %s on %s"
+                             % (self.out_dtype, self.out_shape(), self.device))
+
+    def _ptr(self, t: torch.Tensor) -> int:
+        return int(t.data_ptr())
+
+    # ------------------------------------------------------------------- calls
+    def accumulate(self, x: torch.Tensor):
+        t = self._check_input(x)
+        _check(lib.xcorr_accumulate(self._h, ctypes.c_void_p(self._ptr(x) if t else 0), t))
+
+    def dump(self, out: torch.Tensor | None = None, reset: bool = True):
+        out = self.new_output() if out is None else out
+        self._check_output(out)
+        info = DumpInfo()
+        _check(lib.xcorr_dump(self._h, ctypes.c_void_p(self._ptr(out)), int(bool(reset)),
+                              ctypes.byref(info)))
+        return out, Dump(info.samples_accumulated, info.start_sample, info.n_dumps)
+
+    def accumulate_dump(self, x: torch.Tensor, out: torch.Tensor | None = None,
+                        reset: bool = True):
+        t = self._check_input(x)
+        out = self.new_output() if out is None else out
+        self._check_output(out)
+        info = DumpInfo()
+        _check(lib.xcorr_accumulate_dump(self._h, ctypes.c_void_p(self._ptr(x) if t else 0), t,
+                                         ctypes.c_void_p(self._ptr(out)), int(bool(reset)),
+                                         ctypes.byref(info)))
+        return out, Dump(info.samples_accumulated, info.start_sample, info.n_dumps)
+
+    def query(self) -> PlanInfo:
+        info = PlanInfo()
+        _check(lib.xcorr_query(self._h, ctypes.byref(info)))
+        return info
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib.xcorr_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def correlate(x: torch.Tensor, fmt: str = "ci4", path: str = "i8") -> torch.Tensor:
+    """One-shot: visibilities of one integration window (fused accumulate + dump)."""
+    n_ch, n_in = x.shape[0], x.shape[2]
+    with Plan(n_in, n_ch, fmt, path) as p:
+        out, _ = p.accumulate_dump(x)
+    return out

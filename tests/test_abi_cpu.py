@@ -1,0 +1,110 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, and rejects bad descriptors before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xcorr.h")
+LIB = os.path.join(ROOT, "paper_1401_8288_amd", "libxcorr.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xcorr_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1401_8288_amd import build
+        build.build(verbose=False)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dump",
+              "xcorr_query", "xcorr_destroy"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in declared():
+        assert hasattr(lib, n), n
+
+
+def test_binding_exports_match_header():
+    import torch  # noqa: F401  (the binding loads after torch)
+    from paper_1401_8288_amd import xcorr
+    assert sorted(xcorr.EXPORTS) == declared()
+
+
+def test_version_and_strerror(lib):
+    lib.xcorr_version.restype = ctypes.c_int32
+    assert lib.xcorr_version() >= 100
+    lib.xcorr_strerror.restype = ctypes.c_char_p
+    lib.xcorr_strerror.argtypes = [ctypes.c_int]
+    assert lib.xcorr_strerror(0) == b"ok"
+    assert lib.xcorr_strerror(-1) == b"invalid argument"
+    assert lib.xcorr_strerror(-99) == b"unknown status"
+
+
+def _desc(**kw):
+    import torch  # noqa: F401
+    from paper_1401_8288_amd import xcorr
+    d = dict(n_inputs=64, n_channels=4, fmt="ci4", path="i8")
+    d.update(kw)
+    return xcorr.make_desc(**d)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_inputs=0), -1), (dict(n_channels=0), -1), (dict(n_inputs=-4), -1),
+    (dict(n_inputs=6), -6),             # ci4 needs a multiple of 4 inputs
+    (dict(n_inputs=5, fmt="ci8"), -6),  # ci8 needs a multiple of 2
+    (dict(n_inputs=40000), -6),
+    (dict(flags=0x100), -1), (dict(tile=7), -1)])
+def test_bad_descriptors_rejected_before_any_device_call(kw, status):
+    from paper_1401_8288_amd import xcorr
+    h = ctypes.c_void_p()
+    d = _desc(**kw)
+    assert xcorr.lib.xcorr_plan(ctypes.byref(h), ctypes.byref(d)) == status
+    assert h.value is None
+    assert xcorr.lib.xcorr_last_error()
+
+
+def test_bad_enums_rejected():
+    from paper_1401_8288_amd import xcorr
+    d = _desc()
+    d.format = 7
+    h = ctypes.c_void_p()
+    assert xcorr.lib.xcorr_plan(ctypes.byref(h), ctypes.byref(d)) == -1
+    d = _desc()
+    d.path = 9
+    assert xcorr.lib.xcorr_plan(ctypes.byref(h), ctypes.byref(d)) == -1
+    assert xcorr.lib.xcorr_plan(None, ctypes.byref(_desc())) == -1
+    assert xcorr.lib.xcorr_plan(ctypes.byref(h), None) == -1
+
+
+def test_calls_on_invalid_handles():
+    from paper_1401_8288_amd import xcorr
+    bogus = ctypes.c_void_p(0x1234)
+    assert xcorr.lib.xcorr_accumulate(bogus, None, 0) == -4
+    assert xcorr.lib.xcorr_dump(bogus, None, 1, None) == -4
+    assert xcorr.lib.xcorr_accumulate_dump(bogus, None, 0, None, 1, None) == -4
+    assert xcorr.lib.xcorr_query(bogus, None) == -4
+    assert xcorr.lib.xcorr_destroy(None) == -4
+    assert xcorr.lib.xcorr_destroy(bogus) == -4
+
+
+@pytest.mark.parametrize("n_in,fmt,path", [(64, "ci4", "i8"), (512, "ci4", "i8"),
+                                           (2048, "ci8", "i8"), (512, "ci4", "f32")])
+def test_plan_bytes_is_the_accumulator(n_in, fmt, path):
+    from paper_1401_8288_amd import xcorr
+    nb = n_in * (n_in + 1) // 2
+    got = xcorr.plan_bytes(n_in, 4096, fmt, path)
+    acc = nb * 4096 * 2 * (8 if path == "i8" else 4)
+    assert acc <= got < acc + 65536

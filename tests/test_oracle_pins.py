@@ -281,3 +281,13 @@ def test_constant_input_past_int32(fmt, re, im, per_sample):
     assert (v[..., 0] == n_t * per_sample).all()
     assert (v[..., 1] == 0).all()
     assert v[0, 0, 0] > 2 ** 31
+
+
+@pytest.mark.parametrize("fmt", ["ci4", "ci8"])
+def test_row_range_matches_full_channel(fmt):
+    x = np_(synth.random_input(3, 50, 23, fmt, seed=18))
+    full = oracle.correlate(x, fmt)
+    for r0, rc in ((0, 1), (5, 7), (22, 1), (0, 23)):
+        a = r0 * (r0 + 1) // 2
+        b = (r0 + rc) * (r0 + rc + 1) // 2
+        np.testing.assert_array_equal(oracle.correlate_rows(x, fmt, 2, r0, rc), full[2, a:b])
