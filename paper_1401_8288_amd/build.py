@@ -36,13 +36,19 @@ def flags() -> list[str]:
             "-I", INCLUDE, "-I", CSRC]
 
 
+# Per-source extra flags.  The int8 kernel keeps its MFMA accumulators in
+# VGPRs: with accumulator registers chosen by the default heuristic the
+# compiler rotates them through copies on every loop iteration.
+EXTRA_FLAGS = {"xcorr_i8.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=true"]}
+
+
 def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + flags() + ["-c", src, "-o", obj]
+    cmd = [hipcc()] + flags() + EXTRA_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # drop the host pass's note about the disabled packed-fp32 feature
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)

@@ -69,20 +69,25 @@ bool live(xcorr_plan_t p)
     return p != nullptr && g_live.count(p) != 0;
 }
 
-// Lower-triangle work items for W row blocks of 64 inputs.  Off-diagonal
-// pairs of row-block pairs become four FULL tiles; a diagonal pair becomes
-// two DIAG tiles plus the off-diagonal tile between them split in two halves,
-// so that no wave of the workgroup carries more than 10 of 16 blocks.
-void plan_items(int W, std::vector<WorkItem>& items, int& ch_group)
+WorkItem blank_item()
 {
+    WorkItem it;
+    for (int k = 0; k < kSlots; ++k) { it.rb[k] = -1; it.ch[k] = 0; }
+    for (int w = 0; w < kMaxWaves; ++w) { it.wi[w] = 0; it.wj[w] = 0; it.kind[w] = KIND_NONE; }
+    it.pad[0] = it.pad[1] = it.pad[2] = 0;
+    return it;
+}
+
+// Lower-triangle work items for W row blocks of 64 inputs, four waves per
+// workgroup (fp16 and fp32 kernels).  Off-diagonal pairs of row-block pairs
+// become four FULL tiles; a diagonal pair becomes two DIAG tiles plus the
+// off-diagonal tile between them split in two halves, so that no wave of the
+// workgroup carries more than 10 of 16 blocks.
+void plan_items4(int W, std::vector<WorkItem>& items, int& ch_group)
+{
+    constexpr int kWaves = 4;
     items.clear();
-    auto blank = []() {
-        WorkItem it;
-        for (int k = 0; k < kSlots; ++k) { it.rb[k] = -1; it.ch[k] = 0; }
-        for (int w = 0; w < kWaves; ++w) { it.wi[w] = 0; it.wj[w] = 0; it.kind[w] = KIND_NONE; }
-        it.pad[0] = it.pad[1] = 0;
-        return it;
-    };
+    auto blank = blank_item;
     if (W == 1) {
         // one row block per channel: four channels per workgroup, one DIAG tile each
         ch_group = kWaves;
@@ -131,6 +136,78 @@ void plan_items(int W, std::vector<WorkItem>& items, int& ch_group)
             items.push_back(it);
         }
     }
+}
+
+// The same decomposition for eight waves per workgroup (int8 kernel), with at
+// most 8 blocks per wave: every FULL tile becomes two HALF waves, a diagonal
+// tile two balanced DIAG_A / DIAG_B waves of 5 blocks, and the off-diagonal
+// tile inside a diagonal pair four QUART waves of 4 blocks, so a diagonal
+// work item costs 5/8 of an off-diagonal one.
+void plan_items8(int W, std::vector<WorkItem>& items, int& ch_group)
+{
+    items.clear();
+    if (W == 1) {
+        // one row block per channel: four channels per workgroup
+        ch_group = 4;
+        WorkItem it = blank_item();
+        for (int s = 0; s < kSlots; ++s) {
+            it.rb[s] = 0;
+            it.ch[s] = (int8_t)s;
+            for (int h = 0; h < 2; ++h) {
+                it.wi[2 * s + h] = it.wj[2 * s + h] = (int8_t)s;
+                it.kind[2 * s + h] = h ? KIND_DIAG_B : KIND_DIAG_A;
+            }
+        }
+        items.push_back(it);
+        return;
+    }
+    ch_group = 1;
+    const int SB = (W + 1) / 2;
+    for (int R = 0; R < SB; ++R) {
+        int rr[2], nr = 0;
+        for (int k = 0; k < 2; ++k) if (2 * R + k < W) rr[nr++] = 2 * R + k;
+        for (int S = 0; S <= R; ++S) {
+            WorkItem it = blank_item();
+            int w = 0;
+            auto add = [&](int si, int sj, int kind) {
+                it.wi[w] = (int8_t)si;
+                it.wj[w] = (int8_t)sj;
+                it.kind[w] = (int8_t)kind;
+                ++w;
+            };
+            if (S < R) {
+                int ss[2], ns = 0;
+                for (int k = 0; k < 2; ++k) if (2 * S + k < W) ss[ns++] = 2 * S + k;
+                int slot = 0;
+                for (int k = 0; k < nr; ++k) it.rb[slot++] = (int16_t)rr[k];
+                for (int k = 0; k < ns; ++k) it.rb[slot++] = (int16_t)ss[k];
+                for (int a = 0; a < nr; ++a)
+                    for (int b = 0; b < ns; ++b) {
+                        add(a, nr + b, KIND_HALF0);
+                        add(a, nr + b, KIND_HALF1);
+                    }
+            } else if (nr == 2) {
+                it.rb[0] = (int16_t)rr[0];
+                it.rb[1] = (int16_t)rr[1];
+                for (int q = 0; q < 4; ++q) add(1, 0, KIND_QUART0 + q);
+                add(0, 0, KIND_DIAG_A);
+                add(0, 0, KIND_DIAG_B);
+                add(1, 1, KIND_DIAG_A);
+                add(1, 1, KIND_DIAG_B);
+            } else {
+                it.rb[0] = (int16_t)rr[0];
+                add(0, 0, KIND_DIAG_A);
+                add(0, 0, KIND_DIAG_B);
+            }
+            items.push_back(it);
+        }
+    }
+}
+
+void plan_items(int path, int W, std::vector<WorkItem>& items, int& ch_group)
+{
+    if (path == XCORR_PATH_I8_MFMA) plan_items8(W, items, ch_group);
+    else plan_items4(W, items, ch_group);
 }
 
 size_t elem_bytes(int path) { return path == XCORR_PATH_I8_MFMA ? 8 : 4; }
@@ -251,7 +328,7 @@ xcorr_status xcorr_plan_bytes(const xcorr_plan_desc* d, size_t* bytes)
     if (!bytes) return fail(XCORR_ERR_ARG, "null output");
     std::vector<WorkItem> items;
     int cg;
-    plan_items((d->n_inputs + kRowBlock - 1) / kRowBlock, items, cg);
+    plan_items(d->path, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, cg);
     *bytes = plan_device_bytes(d, items.size());
     return XCORR_OK;
 }
@@ -288,7 +365,7 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
     p->fold_bound = std::min<int64_t>(p->fold_bound, ((int64_t)1 << 31) / row - 1);
 
     std::vector<WorkItem> items;
-    plan_items((d->n_inputs + kRowBlock - 1) / kRowBlock, items, p->ch_group);
+    plan_items(d->path, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, p->ch_group);
     p->n_items = (int)items.size();
     p->n_groups = (d->n_channels + p->ch_group - 1) / p->ch_group;
     const int64_t blocks = (int64_t)p->n_items * p->n_groups;

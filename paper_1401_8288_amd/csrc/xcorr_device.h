@@ -49,8 +49,19 @@ __device__ __forceinline__ uint32_t column_offset(int input, int n_inputs, int b
 
 __device__ __forceinline__ constexpr bool block_on(int kind, int bi, int bj)
 {
-    return kind == KIND_FULL || (kind == KIND_DIAG && bj <= bi) ||
-           (kind == KIND_HALF0 && bj < 2) || (kind == KIND_HALF1 && bj >= 2);
+    return (kind_mask(kind) >> (4 * bi + bj)) & 1u;
+}
+
+// True if the kind owns any block in column bj.
+__device__ __forceinline__ constexpr bool column_on(int kind, int bj)
+{
+    return (kind_mask(kind) & (0x1111u << bj)) != 0;
+}
+
+// True if the kind owns any block in row bi.
+__device__ __forceinline__ constexpr bool row_on(int kind, int bi)
+{
+    return (kind_mask(kind) & (0xFu << (4 * bi))) != 0;
 }
 
 }  // namespace xcorr

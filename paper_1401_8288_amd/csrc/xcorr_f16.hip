@@ -217,12 +217,12 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJob& w, 
 }
 
 template <int FMT>
-__global__ void __launch_bounds__(kThreads, 1) xcorr_f16_kernel(LaunchArgs a)
+__global__ void __launch_bounds__(64 * kWavesF16, 1) xcorr_f16_kernel(LaunchArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
     const int b = work_item_index(blockIdx.x, a.n_blocks, a.xcd_map);
     if (b >= a.n_blocks) return;
-    const WaveJob w = wave_job(a, b);
+    const WaveJob w = wave_job<kWavesF16>(a, b);
     const int lane = threadIdx.x & 63;
     switch (w.kind) {
     case KIND_FULL:  run_tile<FMT, KIND_FULL>(a, w, lane, lds); break;
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_f16_kernel(LaunchArgs a)
 
 hipError_t launch_f16(const LaunchArgs& a, int fmt, hipStream_t s)
 {
-    const dim3 grid(launch_blocks(a.n_blocks, a.xcd_map)), block(kThreads);
+    const dim3 grid(launch_blocks(a.n_blocks, a.xcd_map)), block(64 * kWavesF16);
     if (fmt == 0) hipLaunchKernelGGL(xcorr_f16_kernel<0>, grid, block, 0, s, a);
     else          hipLaunchKernelGGL(xcorr_f16_kernel<1>, grid, block, 0, s, a);
     return hipGetLastError();

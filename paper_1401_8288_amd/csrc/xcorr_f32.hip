@@ -150,12 +150,12 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJob& w, 
 }
 
 template <int FMT>
-__global__ void __launch_bounds__(kThreads, 1) xcorr_f32_kernel(LaunchArgs a)
+__global__ void __launch_bounds__(64 * kWavesF32, 1) xcorr_f32_kernel(LaunchArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
     const int b = work_item_index(blockIdx.x, a.n_blocks, a.xcd_map);
     if (b >= a.n_blocks) return;
-    const WaveJob w = wave_job(a, b);
+    const WaveJob w = wave_job<kWavesF32>(a, b);
     run_tile<FMT>(a, w, threadIdx.x & 63, lds);
 }
 
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_f32_kernel(LaunchArgs a)
 
 hipError_t launch_f32(const LaunchArgs& a, int fmt, hipStream_t s)
 {
-    const dim3 grid(launch_blocks(a.n_blocks, a.xcd_map)), block(kThreads);
+    const dim3 grid(launch_blocks(a.n_blocks, a.xcd_map)), block(64 * kWavesF32);
     if (fmt == 0) hipLaunchKernelGGL(xcorr_f32_kernel<0>, grid, block, 0, s, a);
     else          hipLaunchKernelGGL(xcorr_f32_kernel<1>, grid, block, 0, s, a);
     return hipGetLastError();

@@ -10,32 +10,53 @@ namespace xcorr {
 // Work decomposition.
 //
 // The lower triangle of one channel's N_i x N_i visibility matrix is cut into
-// 64 x 64 "wave tiles" (one wavefront accumulates one tile for the whole time
-// window).  A workgroup of four wavefronts stages up to four 64-input "row
-// blocks" of the channel in LDS per 64-sample step; each wave reads the row
-// block of its tile's rows (I) and of its columns (J).  A tile is computed as
-// a 4 x 4 grid of 16 x 16 blocks; its kind says which blocks:
-//   FULL  all 16 (off-diagonal tile)
-//   DIAG  the 10 blocks with bj <= bi (tile on the diagonal, I == J)
-//   HALF0 columns 0-31 (bj 0, 1) of an off-diagonal tile
-//   HALF1 columns 32-63 (bj 2, 3)
+// 64 x 64 tiles.  A workgroup stages up to four 64-input "row blocks" of the
+// channel in LDS per time step; each wavefront accumulates a part of one tile
+// (the rows of one staged row block, I, against the columns of another, J)
+// for the whole time window.  A tile is a 4 x 4 grid of 16 x 16 blocks; a
+// wave's kind says which blocks it owns:
+//   FULL    all 16 (off-diagonal tile)
+//   DIAG    the 10 blocks with bj <= bi (diagonal tile, I == J)
+//   HALF0/1 the 8 blocks of columns bj 0-1 / 2-3
+//   DIAG_A  (0,0) (1,0) (1,1) (3,2) (3,3)  }  the diagonal tile in two
+//   DIAG_B  (2,0) (2,1) (2,2) (3,0) (3,1)  }  balanced halves of 5 blocks
+//   QUART_k the 4 blocks of column bj = k
+// The four-wave kernels (fp16, fp32) use FULL/DIAG/HALF tiles; the eight-wave
+// int8 kernel uses at most 8 blocks per wave so that its int32 accumulators
+// fit two waves per SIMD.
 // ---------------------------------------------------------------------------
-enum TileKind : int8_t { KIND_NONE = 0, KIND_FULL = 1, KIND_DIAG = 2, KIND_HALF0 = 3, KIND_HALF1 = 4 };
+enum TileKind : int8_t {
+    KIND_NONE = 0, KIND_FULL = 1, KIND_DIAG = 2, KIND_HALF0 = 3, KIND_HALF1 = 4,
+    KIND_DIAG_A = 5, KIND_DIAG_B = 6, KIND_QUART0 = 7, KIND_QUART1 = 8, KIND_QUART2 = 9,
+    KIND_QUART3 = 10
+};
 
-constexpr int kWaves = 4;          // wavefronts per workgroup
-constexpr int kThreads = 64 * kWaves;
+// Bit 4*bi + bj set <=> block (bi, bj) belongs to the kind.
+__host__ __device__ constexpr uint32_t kind_mask(int kind)
+{
+    return kind == KIND_FULL    ? 0xFFFFu
+         : kind == KIND_DIAG    ? 0xF731u
+         : kind == KIND_HALF0   ? 0x3333u
+         : kind == KIND_HALF1   ? 0xCCCCu
+         : kind == KIND_DIAG_A  ? 0xC031u
+         : kind == KIND_DIAG_B  ? 0x3700u
+         : kind >= KIND_QUART0 && kind <= KIND_QUART3 ? (0x1111u << (kind - KIND_QUART0))
+         : 0u;
+}
+
 constexpr int kSlots = 4;          // row blocks staged per workgroup
-constexpr int kRowBlock = 64;      // inputs per row block (= wave tile edge)
+constexpr int kRowBlock = 64;      // inputs per row block (= tile edge)
+constexpr int kMaxWaves = 8;
 
 struct WorkItem {                  // one workgroup's job inside one channel group
     int16_t rb[kSlots];            // row block staged in each slot, -1 = unused
     int8_t ch[kSlots];             // channel offset of each slot within its group
-    int8_t wi[kWaves];             // per wave: slot holding the tile's rows (I)
-    int8_t wj[kWaves];             // per wave: slot holding the tile's columns (J)
-    int8_t kind[kWaves];           // per wave: TileKind
-    int32_t pad[2];
+    int8_t wi[kMaxWaves];          // per wave: slot holding the tile's rows (I)
+    int8_t wj[kMaxWaves];          // per wave: slot holding the tile's columns (J)
+    int8_t kind[kMaxWaves];        // per wave: TileKind
+    int32_t pad[3];
 };
-static_assert(sizeof(WorkItem) == 32, "WorkItem layout");
+static_assert(sizeof(WorkItem) == 48, "WorkItem layout");
 
 // Arguments of one accumulation launch (one time chunk).
 struct LaunchArgs {
@@ -65,25 +86,33 @@ __device__ inline int work_item_index(int block, int n_blocks, int xcd_map)
     return (block & 7) * per + (block >> 3);
 }
 
-// One wave's share of a work item, read once into scalar registers.
-struct WaveJob {
-    int wave;                      // wave index in the workgroup (slot it stages)
-    int stage_rb;                  // row block this wave stages, -1 = none
-    int stage_ch;                  // channel of the staged row block
-    int kind;                      // TileKind of this wave's tile
+// One wave's share of a work item, read once into scalar registers.  With
+// WAVES waves per workgroup, slot s is staged by waves s * WAVES/4 ...
+template <int WAVES>
+struct WaveJobT {
+    int wave;                      // wave index in the workgroup
+    int stage_part;                // which share of its slot this wave stages
+    int stage_slot;                // slot this wave stages
+    int stage_rb;                  // row block of that slot, -1 = none
+    int stage_ch;                  // channel of that slot
+    int kind;                      // TileKind of this wave's tile part
     int si, sj;                    // slots of the tile's rows and columns
     int rb_i, rb_j;                // row blocks of the tile's rows and columns
     int tile_ch;                   // channel of the tile
 };
 
-__device__ inline WaveJob wave_job(const LaunchArgs& a, int b)
+template <int WAVES>
+__device__ inline WaveJobT<WAVES> wave_job(const LaunchArgs& a, int b)
 {
+    constexpr int per_slot = WAVES / kSlots;
     const int group = b / a.n_items;
     const WorkItem* it = a.items + (b - group * a.n_items);
-    WaveJob w;
+    WaveJobT<WAVES> w;
     w.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    w.stage_rb = __builtin_amdgcn_readfirstlane(it->rb[w.wave]);
-    w.stage_ch = group * a.ch_group + __builtin_amdgcn_readfirstlane(it->ch[w.wave]);
+    w.stage_slot = w.wave / per_slot;
+    w.stage_part = w.wave - w.stage_slot * per_slot;
+    w.stage_rb = __builtin_amdgcn_readfirstlane(it->rb[w.stage_slot]);
+    w.stage_ch = group * a.ch_group + __builtin_amdgcn_readfirstlane(it->ch[w.stage_slot]);
     w.kind = __builtin_amdgcn_readfirstlane(it->kind[w.wave]);
     w.si = __builtin_amdgcn_readfirstlane(it->wi[w.wave]);
     w.sj = __builtin_amdgcn_readfirstlane(it->wj[w.wave]);
@@ -92,11 +121,17 @@ __device__ inline WaveJob wave_job(const LaunchArgs& a, int b)
     w.tile_ch = group * a.ch_group + __builtin_amdgcn_readfirstlane(it->ch[w.si]);
     return w;
 }
+using WaveJob = WaveJobT<4>;
 
 inline int launch_blocks(int n_blocks, int xcd_map)
 {
     return xcd_map ? ((n_blocks + 7) >> 3) << 3 : n_blocks;
 }
+
+// Waves per workgroup of each kernel (the host plans work items to match).
+constexpr int kWavesI8 = 8;
+constexpr int kWavesF16 = 4;
+constexpr int kWavesF32 = 4;
 
 // Kernel launchers (one per arithmetic path); return the launch error.
 hipError_t launch_i8(const LaunchArgs& a, int fmt, hipStream_t s);
