@@ -42,13 +42,25 @@ constexpr int kPitch = 80;                 // LDS bytes per row (64 samples + 16
 // Global loads run this many steps ahead of the step they feed: a channel's
 // first reader waits for HBM, and the other workgroups of the channel, which
 // run at the same time on the same XCD, wait for the same lines.
-constexpr int kPrefetch = 4;
+// Kernel variants.  V_CI4: 4-bit samples, staged transposed ([input][time]
+// rows) by byte permutes in registers.  V_CI8: 8-bit samples, the same with
+// separate re and im rows.  V_CI4_TR: 4-bit samples with n_inputs % 16 == 0,
+// staged in their natural [time][input] order by 16-byte loads and stores
+// and transposed by the LDS transpose read (ds_read_b64_tr_b8).
+enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_TR = 2 };
+__device__ __forceinline__ constexpr bool is_ci4(int v) { return v != V_CI8; }
 
-// LDS geometry.  CI4: one part per slot, the raw transposed bytes (re and im
-// nibbles of 64 samples per input row).  CI8: two parts, re rows and im rows.
+constexpr int kPrefetch = 4;
+// Ring depth per variant (a divisor of kPrefetch): the natural-order loads of
+// V_CI4_TR are whole 64-byte row segments and are given two steps.
+template <int FMT>
+__device__ __forceinline__ constexpr int ring_depth() { return FMT == V_CI4_TR ? 2 : kPrefetch; }
+
+// LDS geometry.  CI4: one part per slot, the raw bytes (re and im nibbles)
+// of 64 samples x 64 inputs.  CI8: two parts, re rows and im rows.
 template <int FMT>
 struct Geo {
-    static constexpr int kParts = FMT == 0 ? 1 : 2;
+    static constexpr int kParts = FMT == V_CI8 ? 2 : 1;
     static constexpr int kPart = kRowBlock * kPitch;
     static constexpr int kSlotBytes = kParts * kPart;
     static constexpr int kBufBytes = kSlots * kSlotBytes;
@@ -62,7 +74,7 @@ struct Geo {
 // each, i.e. all 32 banks once.
 template <int FMT>
 struct Stager {
-    static constexpr int kJobs = (FMT == 0) ? 1 : 2;
+    static constexpr int kJobs = (FMT == V_CI4) ? 1 : 2;
     uint32_t r[kPrefetch][kJobs][8];  // ring: slot k % kPrefetch holds step k
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t vofs[kJobs];
@@ -81,11 +93,11 @@ struct Stager {
         kofs = 8 * g;
 #pragma unroll
         for (int j = 0; j < kJobs; ++j) {
-            const int col = (FMT == 0) ? 4 * grp : 2 * (2 * grp + j);
+            const int col = (FMT == V_CI4) ? 4 * grp : 2 * (2 * grp + j);
             row[j] = col;
             const int input = (w.stage_rb < 0 ? 0 : w.stage_rb) * kRowBlock + col;
             vofs[j] = (uint32_t)(8 * g) * (uint32_t)a.row_bytes +
-                      column_offset(input, a.n_inputs, FMT == 0 ? 1 : 2);
+                      column_offset(input, a.n_inputs, FMT == V_CI4 ? 1 : 2);
         }
     }
 
@@ -116,7 +128,7 @@ struct Stager {
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const v2i v{(int)o[0][m], (int)o[1][m]};
-                if (FMT == 0) {
+                if (FMT == V_CI4) {
                     *(v2i*)(slot + (row[j] + m) * kPitch + kofs) = v;
                 } else {
                     // byte columns re(2p), im(2p), re(2p+1), im(2p+1)
@@ -128,12 +140,77 @@ struct Stager {
     }
 };
 
+// V_CI4_TR staging: each slot is copied in its natural order, one 64-byte row
+// per sample.  The two waves of a slot take 32 rows each, 16 per load: lane l
+// loads 16 bytes (16 inputs) at column 16 * (l % 4) of row
+// ((l / 8) % 4) + 4 * ((l / 4) % 2) + 8 * (l / 32).  Each load instruction
+// reads 16 whole 64-byte row segments, and the 8 lanes of each LDS write
+// cycle cover two rows 4 apart (80 banks, 16 mod 32): all 32 banks once.
+template <>
+struct Stager<V_CI4_TR> {
+    v4i r[ring_depth<V_CI4_TR>()][2];  // ring: slot k % depth holds step k
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t vofs[2];
+    int lofs[2];
+    int row_bytes;
+    int lds_slot;
+
+    __device__ __forceinline__ void init(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane)
+    {
+        lds_slot = w.stage_rb < 0 ? -1 : w.stage_slot;
+        row_bytes = a.row_bytes;
+        rsrc = channel_rsrc(a, w.stage_rb, w.stage_ch);
+        const int q = lane & 3;
+        const int r16 = ((lane >> 3) & 3) + 4 * ((lane >> 2) & 1) + 8 * (lane >> 5);
+        const int input = (w.stage_rb < 0 ? 0 : w.stage_rb) * kRowBlock + 16 * q;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int row = 32 * w.stage_part + 16 * j + r16;
+            vofs[j] = (uint32_t)row * (uint32_t)a.row_bytes + column_offset(input, a.n_inputs, 1);
+            lofs[j] = row * kPitch + 16 * q;
+        }
+    }
+
+    template <int S>
+    __device__ __forceinline__ void load(int k)
+    {
+        const uint32_t step = (uint32_t)(k * kStep) * (uint32_t)row_bytes;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            r[S][j] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(vofs[j] + step), 0, 0));
+    }
+
+    template <int S>
+    __device__ __forceinline__ void store(uint8_t* buf) const
+    {
+        if (lds_slot < 0) return;
+        uint8_t* slot = buf + lds_slot * Geo<V_CI4_TR>::kSlotBytes;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) *(v4i*)(slot + lofs[j]) = r[S][j];
+    }
+};
+
 // Operand fragment of a 16-row block: lane l holds row l % 16 and the 16
 // samples 16 * (l / 16)..+15 of the step (the same sample set for the A and
 // B operands of the MFMA, so the contraction pairs equal samples).
 __device__ __forceinline__ v4i frag(const uint8_t* part, int blk, int lane)
 {
     return *(const v4i*)(part + (16 * blk + (lane & 15)) * kPitch + 16 * (lane >> 4));
+}
+
+// The same fragment from a natural-order slot ([sample][input] rows): within
+// each group of 16 lanes, lane j points at 8 bytes (inputs 8*(j%2)..+7 of the
+// block) of sample row j/2, and the transpose read returns to lane L the
+// byte of input L from each of the 8 rows.  Two reads give the 16 samples.
+__device__ __forceinline__ v4i frag_tr(const uint8_t* part, int blk, int lane)
+{
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) v2i lds_v2i;
+    const int j = lane & 15;
+    const uint8_t* p = part + (16 * (lane >> 4) + (j >> 1)) * kPitch + 16 * blk + 8 * (j & 1);
+    const v2i lo = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i*)(p));
+    const v2i hi = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i*)(p + 8 * kPitch));
+    return v4i{lo.x, lo.y, hi.x, hi.y};
 }
 
 // CI4 byte = (re << 4) | (im & 0xF): masking gives 16*re and 16*im as exact int8.
@@ -152,43 +229,117 @@ struct Acc {
     v4i re[4][4], ab[4][4], ba[4][4];
 };
 
-// Reads the operands of the blocks the kind owns and runs its MFMAs.
+// MFMA operands of one step: re and im fragments of the I and J row blocks
+// (only the blocks the kind uses are set).
+struct Ops {
+    v4i ia[4], ib[4], ja[4], jb[4];
+};
+
+// Fragments as read from LDS.  CI4: raw bytes of the I and J blocks, split
+// into operands by prepare().  CI8: the operands themselves.
+template <int FMT>
+struct Raw;
+template <>
+struct Raw<V_CI4> {
+    v4i ri[4], rj[4];
+};
+template <>
+struct Raw<V_CI4_TR> {
+    v4i ri[4], rj[4];
+};
+template <>
+struct Raw<V_CI8> {
+    Ops o;
+};
+
+template <int KIND>
+__device__ __forceinline__ constexpr bool same_block(int)
+{
+    return KIND == KIND_DIAG || KIND == KIND_DIAG_A || KIND == KIND_DIAG_B;
+}
+
+template <int KIND>
+__device__ __forceinline__ constexpr bool need_i(int b)
+{
+    return row_on(KIND, b) || (same_block<KIND>(0) && column_on(KIND, b));
+}
+
+template <int KIND>
+__device__ __forceinline__ constexpr bool need_j(int b)
+{
+    return column_on(KIND, b) && !same_block<KIND>(0);
+}
+
 template <int FMT, int KIND>
-__device__ __forceinline__ void mfma_step(const uint8_t* buf, int si, int sj, int lane, Acc& c)
+__device__ __forceinline__ void read_raw(const uint8_t* buf, int si, int sj, int lane, Raw<FMT>& r)
 {
     const uint8_t* pI = buf + si * Geo<FMT>::kSlotBytes;
     const uint8_t* pJ = buf + sj * Geo<FMT>::kSlotBytes;
-    v4i ia[4], ib[4], ja[4], jb[4];
-    constexpr bool same = (KIND == KIND_DIAG || KIND == KIND_DIAG_A || KIND == KIND_DIAG_B);
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        if (row_on(KIND, b) || (same && column_on(KIND, b))) {
-            if (FMT == 0) {
-                const v4i r = frag(pI, b, lane);
-                ia[b] = hi16(r);
-                ib[b] = lo16(r);
-            } else {
-                ia[b] = frag(pI, b, lane);
-                ib[b] = frag(pI + Geo<FMT>::kPart, b, lane);
+        if constexpr (FMT == V_CI4) {
+            if (need_i<KIND>(b)) r.ri[b] = frag(pI, b, lane);
+            if (need_j<KIND>(b)) r.rj[b] = frag(pJ, b, lane);
+        } else if constexpr (FMT == V_CI4_TR) {
+            if (need_i<KIND>(b)) r.ri[b] = frag_tr(pI, b, lane);
+            if (need_j<KIND>(b)) r.rj[b] = frag_tr(pJ, b, lane);
+        } else {
+            if (need_i<KIND>(b)) {
+                r.o.ia[b] = frag(pI, b, lane);
+                r.o.ib[b] = frag(pI + Geo<FMT>::kPart, b, lane);
+            }
+            if (need_j<KIND>(b)) {
+                r.o.ja[b] = frag(pJ, b, lane);
+                r.o.jb[b] = frag(pJ + Geo<FMT>::kPart, b, lane);
             }
         }
     }
+}
+
+template <int FMT, int KIND>
+__device__ __forceinline__ void prepare(const Raw<FMT>& r, Ops& o)
+{
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        if (!column_on(KIND, b)) continue;
-        if (same) {
-            ja[b] = ia[b];
-            jb[b] = ib[b];
-        } else if (FMT == 0) {
-            const v4i r = frag(pJ, b, lane);
-            ja[b] = hi16(r);
-            jb[b] = lo16(r);
+        if constexpr (is_ci4(FMT)) {
+            if (need_i<KIND>(b)) {
+                o.ia[b] = hi16(r.ri[b]);
+                o.ib[b] = lo16(r.ri[b]);
+            }
+            if (need_j<KIND>(b)) {
+                o.ja[b] = hi16(r.rj[b]);
+                o.jb[b] = lo16(r.rj[b]);
+            }
         } else {
-            ja[b] = frag(pJ, b, lane);
-            jb[b] = frag(pJ + Geo<FMT>::kPart, b, lane);
+            if (need_i<KIND>(b)) { o.ia[b] = r.o.ia[b]; o.ib[b] = r.o.ib[b]; }
+            if (need_j<KIND>(b)) { o.ja[b] = r.o.ja[b]; o.jb[b] = r.o.jb[b]; }
+        }
+        if (same_block<KIND>(0) && column_on(KIND, b)) {
+            o.ja[b] = o.ia[b];
+            o.jb[b] = o.ib[b];
         }
     }
-    // term-major order: the two MFMAs into one Re accumulator are far apart
+}
+
+template <int KIND>
+__device__ __forceinline__ constexpr int n_frags()
+{
+    int n = 0;
+    for (int b = 0; b < 4; ++b) n += (need_i<KIND>(b) ? 1 : 0) + (need_j<KIND>(b) ? 1 : 0);
+    return n;
+}
+
+template <int KIND>
+__device__ __forceinline__ constexpr int n_blocks()
+{
+    return __builtin_popcount(kind_mask(KIND));
+}
+
+// The MFMAs of one step, term-major so that the two MFMAs into one Re
+// accumulator are far apart.
+template <int KIND>
+__device__ __forceinline__ void mma(const Ops& o, Acc& c)
+{
 #pragma unroll
     for (int term = 0; term < 4; ++term)
 #pragma unroll
@@ -196,27 +347,68 @@ __device__ __forceinline__ void mfma_step(const uint8_t* buf, int si, int sj, in
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi) {
                 if (!block_on(KIND, bi, bj)) continue;
-                if (term == 0) c.re[bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ia[bi], ja[bj], c.re[bi][bj], 0, 0, 0);
-                if (term == 1) c.ab[bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ia[bi], jb[bj], c.ab[bi][bj], 0, 0, 0);
-                if (term == 2) c.ba[bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ib[bi], ja[bj], c.ba[bi][bj], 0, 0, 0);
-                if (term == 3) c.re[bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ib[bi], jb[bj], c.re[bi][bj], 0, 0, 0);
+                if (term == 0) c.re[bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(o.ia[bi], o.ja[bj], c.re[bi][bj], 0, 0, 0);
+                if (term == 1) c.ab[bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(o.ia[bi], o.jb[bj], c.ab[bi][bj], 0, 0, 0);
+                if (term == 2) c.ba[bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(o.ib[bi], o.ja[bj], c.ba[bi][bj], 0, 0, 0);
+                if (term == 3) c.re[bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(o.ib[bi], o.jb[bj], c.re[bi][bj], 0, 0, 0);
             }
 }
 
-// Step k, k % kPrefetch == S: load step k + kPrefetch into ring slot S, run
-// the MFMAs of step k from LDS buffer k%2, write step k+1 from ring slot
-// (S+1) % kPrefetch into buffer (k+1)%2.
+// Three LDS buffers, step k in buffer k % 3.  CI4 step k: load the samples
+// of step k + kPrefetch into ring slot S = k % kPrefetch, read the raw
+// fragments of step k+1, run the MFMAs of step k from registers, split the
+// step-k+1 fragments into operands, and write step k+2 (ring slot
+// (S+2) % kPrefetch) into buffer (k+2) % 3.  The MFMAs are interleaved with
+// the independent vector work of the next steps.  Buffer (k+2) % 3 last held
+// step k-1, whose fragments were read in step k-2; buffer (k+1) % 3 was
+// written in step k-1.  CI8 fragments are twice as large: they are read at
+// the start of their own step from buffer k % 3.
 template <int FMT, int KIND, int S>
 __device__ __forceinline__ void pipeline_step(int k, Stager<FMT>& st, uint8_t* lds, int si, int sj,
-                                              int lane, Acc& c)
+                                              int lane, Ops& ops, Acc& c)
 {
     constexpr int B = Geo<FMT>::kBufBytes;
-    st.template load<S>(k + kPrefetch);
-    __builtin_amdgcn_sched_barrier(0);
-    if (KIND != KIND_NONE) mfma_step<FMT, KIND>(lds + (k & 1) * B, si, sj, lane, c);
-    __builtin_amdgcn_sched_barrier(0);
-    st.template store<(S + 1) % kPrefetch>(lds + ((k + 1) & 1) * B);
-    __syncthreads();
+    uint8_t* next = lds + ((k + 1) % 3) * B;
+    uint8_t* after = lds + ((k + 2) % 3) * B;
+    constexpr int D = ring_depth<FMT>();
+    st.template load<S % D>(k + D);
+    if constexpr (is_ci4(FMT)) {
+        Raw<FMT> raw;
+        Ops nx;
+        if (KIND != KIND_NONE) {
+            read_raw<FMT, KIND>(next, si, sj, lane, raw);
+            mma<KIND>(ops, c);
+            prepare<FMT, KIND>(raw, nx);
+        }
+        st.template store<(S + 2) % D>(after);
+        if (KIND != KIND_NONE) {
+            // issue order: global loads, fragment reads, then MFMAs each
+            // followed by a few vector instructions, then the LDS writes
+            constexpr int nm = 4 * n_blocks<KIND>();
+            constexpr int n_vmem = FMT == V_CI4_TR ? 2 : 8;
+            constexpr int n_dsr = n_frags<KIND>() * (FMT == V_CI4_TR ? 2 : 1);
+            __builtin_amdgcn_sched_group_barrier(0x020, n_vmem, 0);   // VMEM read
+            __builtin_amdgcn_sched_group_barrier(0x100, n_dsr, 0);    // DS read
+#pragma unroll
+            for (int m = 0; m < nm; ++m) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);    // VALU
+            }
+            __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);        // DS write
+        }
+        __syncthreads();
+        ops = nx;
+    } else {
+        if (KIND != KIND_NONE) {
+            Raw<FMT> raw;
+            read_raw<FMT, KIND>(lds + (k % 3) * B, si, sj, lane, raw);
+            prepare<FMT, KIND>(raw, ops);
+            mma<KIND>(ops, c);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        st.template store<(S + 2) % D>(after);
+        __syncthreads();
+    }
 }
 
 template <int FMT, int KIND>
@@ -239,31 +431,34 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
         }
     const int si = w.si, sj = w.sj;
 
-    // Two LDS buffers: step k is read from buffer k%2 while the samples of
-    // step k+1 (loaded kPrefetch steps earlier into ring slot (k+1) %
-    // kPrefetch) are written to buffer (k+1)%2 at its end; the barrier that
-    // closes step k-1 separates those writes from the last reads of buffer
-    // (k+1)%2.  The loads of step k+kPrefetch go into the ring slot that held
-    // step k.  Loads past the window read zeros and the stores they feed go
-    // to a buffer no later step reads, so the steps need no branches.
-#pragma unroll
-    for (int s = 0; s < kPrefetch; ++s) {
-        if (s == 0) st.template load<0>(0);
-        if (s == 1) st.template load<1>(1);
-        if (s == 2) st.template load<2>(2);
-        if (s == 3) st.template load<3>(3);
+    // Prologue: samples of steps 0..kPrefetch-1 into the ring, steps 0 and 1
+    // into LDS buffers 0 and 1, operands of step 0.  Loads past the window
+    // read zeros, and a step past it multiplies zeros, so the steps run in
+    // unconditional groups of kPrefetch; the compiler can then count the
+    // loads in flight across the loop back-edge and waits only for the
+    // oldest group.
+    static_assert(kPrefetch == 4, "the unrolled ring below assumes four slots");
+    constexpr int D = ring_depth<FMT>();
+    st.template load<0>(0);
+    st.template load<1 % D>(1);
+    if (D == 4) {
+        st.template load<2 % D>(2);
+        st.template load<3 % D>(3);
     }
     st.template store<0>(lds);
+    st.template store<1 % D>(lds + Geo<FMT>::kBufBytes);
     __syncthreads();
-    // The steps run in groups of kPrefetch without conditions (a step past the
-    // window multiplies zeros), so that the compiler can count the loads in
-    // flight across the loop back-edge and wait only for the oldest group.
-    static_assert(kPrefetch == 4, "the unrolled ring below assumes four slots");
+    Ops ops;
+    if (is_ci4(FMT) && KIND != KIND_NONE) {
+        Raw<FMT> raw;
+        read_raw<FMT, KIND>(lds, si, sj, lane, raw);
+        prepare<FMT, KIND>(raw, ops);
+    }
     for (int k0 = 0; k0 < nk; k0 += kPrefetch) {
-        pipeline_step<FMT, KIND, 0>(k0 + 0, st, lds, si, sj, lane, c);
-        pipeline_step<FMT, KIND, 1>(k0 + 1, st, lds, si, sj, lane, c);
-        pipeline_step<FMT, KIND, 2>(k0 + 2, st, lds, si, sj, lane, c);
-        pipeline_step<FMT, KIND, 3>(k0 + 3, st, lds, si, sj, lane, c);
+        pipeline_step<FMT, KIND, 0>(k0 + 0, st, lds, si, sj, lane, ops, c);
+        pipeline_step<FMT, KIND, 1>(k0 + 1, st, lds, si, sj, lane, ops, c);
+        pipeline_step<FMT, KIND, 2>(k0 + 2, st, lds, si, sj, lane, ops, c);
+        pipeline_step<FMT, KIND, 3>(k0 + 3, st, lds, si, sj, lane, ops, c);
     }
     if (KIND == KIND_NONE) return;
 
@@ -272,7 +467,7 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
     const int ch = w.tile_ch;
     if (ch >= a.n_channels) return;
     const int i0 = w.rb_i * kRowBlock, j0 = w.rb_j * kRowBlock;
-    const int shift = (FMT == 0) ? 8 : 0;
+    const int shift = is_ci4(FMT) ? 8 : 0;
     const int64_t nb = (int64_t)a.n_inputs * (a.n_inputs + 1) / 2;
     const int64_t* src = (const int64_t*)a.src;
     int64_t* dst = (int64_t*)a.dst;
@@ -305,7 +500,7 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
 template <int FMT>
 __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_kernel(LaunchArgs a)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * Geo<FMT>::kBufBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[3 * Geo<FMT>::kBufBytes];
     const int b = work_item_index(blockIdx.x, a.n_blocks, a.xcd_map);
     if (b >= a.n_blocks) return;
     const WaveJobT<kWaves> w = wave_job<kWaves>(a, b);
@@ -328,8 +523,9 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_kernel(LaunchArgs a)
 hipError_t launch_i8(const LaunchArgs& a, int fmt, hipStream_t s)
 {
     const dim3 grid(launch_blocks(a.n_blocks, a.xcd_map)), block(kThreads);
-    if (fmt == 0) hipLaunchKernelGGL(xcorr_i8_kernel<0>, grid, block, 0, s, a);
-    else          hipLaunchKernelGGL(xcorr_i8_kernel<1>, grid, block, 0, s, a);
+    if (fmt == 1)                  hipLaunchKernelGGL(xcorr_i8_kernel<V_CI8>, grid, block, 0, s, a);
+    else if (a.n_inputs % 16 == 0) hipLaunchKernelGGL(xcorr_i8_kernel<V_CI4_TR>, grid, block, 0, s, a);
+    else                           hipLaunchKernelGGL(xcorr_i8_kernel<V_CI4>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 
