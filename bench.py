@@ -30,6 +30,11 @@ PEAK_INT8_TOPS = 5000.0       # MI355X dense int8 MFMA, vendor figure
 PEAK_FP16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# HBM-traffic record of the int8 kernel (FETCH_SIZE / WRITE_SIZE counters on
+# this workload plus a copy-kernel calibration), tied to the kernel sources.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xcorr_i8_lwa_traffic.md")
+KERNEL_SOURCES = ("paper_1401_8288_amd/csrc/xcorr_i8.hip", "paper_1401_8288_amd/csrc/xcorr_device.h",
+                  "paper_1401_8288_amd/csrc/xcorr_internal.h", "paper_1401_8288_amd/build.py")
 
 
 def log(*a):
@@ -54,6 +59,67 @@ def time_path(torch, xcorr, x, w, path, steps, warmup):
     info = p.query()
     p.close()
     return ms, out, info
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic():
+    """HBM bytes per launch of the int8 kernel from the recorded counters.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are each scaled by the ratio
+    of known bytes to counted bytes for the library's plain copy kernel in the
+    same runs.  None if no record exists or the kernel sources changed since
+    the counters were taken.
+    """
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no record"
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith(("#", " ", "|", "`")):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    try:
+        if rec["kernel_sources_sha256"] != kernel_sources_sha256():
+            return None, "kernel changed since the counters were taken"
+        f_fetch = float(rec["copy_bytes"]) / (1024 * float(rec["copy_fetch_kib"]))
+        f_write = float(rec["copy_bytes"]) / (1024 * float(rec["copy_write_kib"]))
+        t = 1024 * (float(rec["fetch_kib"]) * f_fetch + float(rec["write_kib"]) * f_write)
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None, "incomplete record"
+    return t, "FETCH_SIZE x %.4f + WRITE_SIZE x %.4f (copy-kernel calibration)" % (f_fetch, f_write)
+
+
+def pmc_summary(directory):
+    """Per-kernel averages of rocprofv3 counter CSVs under a directory."""
+    import collections
+    import csv
+    import glob
+    agg = collections.OrderedDict()
+    for f in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)):
+        for r in csv.DictReader(open(f)):
+            key = (r["Kernel_Name"], r["Counter_Name"])
+            agg.setdefault(key, []).append(float(r["Counter_Value"]))
+    for (k, c), v in agg.items():
+        print("%-70s %-30s dispatches=%d avg=%.6g" % (k[:70], c, len(v), sum(v) / len(v)))
+
+
+def copy_calibration(torch, xcorr, x, w):
+    """One non-fused window, then a dump without reset: the library's copy
+    kernel moves exactly output_bytes (read and written)."""
+    p = xcorr.Plan(w.n_inputs, w.n_channels, w.fmt, "i8")
+    out = p.new_output()
+    p.accumulate(x)
+    p.dump(out, reset=False)
+    torch.cuda.synchronize()
+    log("copy calibration: %d bytes copied" % p.query().output_bytes)
+    p.close()
 
 
 def cpu_baseline(w, budget_s=12.0):
@@ -85,7 +151,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-compare", action="store_true", help="skip the fp16 / fp32 kernels")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run the library copy kernel once (for counter calibration)")
+    ap.add_argument("--pmc-summary", metavar="DIR",
+                    help="print per-kernel averages of rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the X-stage shards by channel with no exchange, "
               "so there is no multi-GPU run here (got --gpus %d)" % args.gpus, file=sys.stderr)
@@ -119,7 +192,7 @@ def main():
                    "format": w.fmt, "path": "int8 MFMA, int32 partials, int64 output",
                    "entry_point": "xcorr_accumulate_dump(reset=1)",
                    "work_items": info.work_items},
-        "roofline": {"bound": "mfma", "kernel": "xcorr_i8_kernel<CI4>",
+        "roofline": {"bound": "mfma", "kernel": "xcorr_i8_kernel<V_CI4_DMA>",
                      "achieved": round(tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
                      "frac": round(tops / PEAK_INT8_TOPS, 4), "traffic": None,
                      "algorithmic_ops_per_launch": 8 * cmac,
@@ -127,8 +200,13 @@ def main():
                      "hbm_gbs_algorithmic": round(hbm_bytes / (ms * 1e-3) / 1e9, 1)},
         "pct_int8_peak": round(100 * tops / PEAK_INT8_TOPS, 2),
     }
+    traffic, how = read_traffic()
+    result["roofline"]["traffic"] = traffic
+    result["roofline"]["traffic_source"] = how
     del out
     torch.cuda.empty_cache()
+    if args.copy_calibration:
+        copy_calibration(torch, xcorr, x, w)
 
     if not args.no_compare:
         comp = {}

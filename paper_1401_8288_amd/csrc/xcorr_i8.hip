@@ -30,6 +30,8 @@
 // per sample and term pair); the host splits longer windows.
 #include "xcorr_device.h"
 
+#include <utility>
+
 namespace xcorr {
 namespace {
 
@@ -44,24 +46,37 @@ constexpr int kPitch = 80;                 // LDS bytes per row (64 samples + 16
 // run at the same time on the same XCD, wait for the same lines.
 // Kernel variants.  V_CI4: 4-bit samples, staged transposed ([input][time]
 // rows) by byte permutes in registers.  V_CI8: 8-bit samples, the same with
-// separate re and im rows.  V_CI4_TR: 4-bit samples with n_inputs % 16 == 0,
-// staged in their natural [time][input] order by 16-byte loads and stores
-// and transposed by the LDS transpose read (ds_read_b64_tr_b8).
-enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_TR = 2 };
+// separate re and im rows.  V_CI4_DMA: 4-bit samples with n_inputs % 16 == 0,
+// copied by the buffer unit straight from HBM into LDS in their natural
+// [time][input] order and transposed by the LDS transpose read
+// (ds_read_b64_tr_b8); no vector registers or LDS writes are spent on staging.
+enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_DMA = 2 };
 __device__ __forceinline__ constexpr bool is_ci4(int v) { return v != V_CI8; }
 
 constexpr int kPrefetch = 4;
-// Ring depth per variant (a divisor of kPrefetch): the natural-order loads of
-// V_CI4_TR are whole 64-byte row segments and are given two steps.
+#ifndef XCORR_DMA_DEPTH
+#define XCORR_DMA_DEPTH 8
+#endif
+// V_CI4_DMA: LDS buffers, one per step in flight; the copy of step k + depth
+// is issued while step k runs.
+constexpr int kDmaDepth = XCORR_DMA_DEPTH;
+static_assert(kDmaDepth >= 3 && kDmaDepth <= 8, "DMA depth");
 template <int FMT>
-__device__ __forceinline__ constexpr int ring_depth() { return FMT == V_CI4_TR ? 2 : kPrefetch; }
+__device__ __forceinline__ constexpr int ring_depth() { return kPrefetch; }
+template <int FMT>
+__device__ __forceinline__ constexpr int n_buffers() { return FMT == V_CI4_DMA ? kDmaDepth : 3; }
+// Steps per unrolled loop iteration.
+template <int FMT>
+__device__ __forceinline__ constexpr int group_steps() { return FMT == V_CI4_DMA ? kDmaDepth : kPrefetch; }
 
 // LDS geometry.  CI4: one part per slot, the raw bytes (re and im nibbles)
-// of 64 samples x 64 inputs.  CI8: two parts, re rows and im rows.
+// of 64 samples x 64 inputs, rows of 64 bytes padded to kPitch.  CI8: two
+// parts, re rows and im rows.  V_CI4_DMA: unpadded 64-byte sample rows.
 template <int FMT>
 struct Geo {
     static constexpr int kParts = FMT == V_CI8 ? 2 : 1;
-    static constexpr int kPart = kRowBlock * kPitch;
+    static constexpr int kRowPitch = FMT == V_CI4_DMA ? kRowBlock : kPitch;
+    static constexpr int kPart = kRowBlock * kRowPitch;
     static constexpr int kSlotBytes = kParts * kPart;
     static constexpr int kBufBytes = kSlots * kSlotBytes;
 };
@@ -140,53 +155,50 @@ struct Stager {
     }
 };
 
-// V_CI4_TR staging: each slot is copied in its natural order, one 64-byte row
-// per sample.  The two waves of a slot take 32 rows each, 16 per load: lane l
-// loads 16 bytes (16 inputs) at column 16 * (l % 4) of row
-// ((l / 8) % 4) + 4 * ((l / 4) % 2) + 8 * (l / 32).  Each load instruction
-// reads 16 whole 64-byte row segments, and the 8 lanes of each LDS write
-// cycle cover two rows 4 apart (80 banks, 16 mod 32): all 32 banks once.
+// V_CI4_DMA staging.  A slot holds 64 sample rows of 64 bytes; 16-byte chunk
+// q of row r sits at position q ^ swz(r).  The swizzle spreads the rows that
+// one transpose read touches over all LDS banks (bits 1 and 2 of the row
+// separate the rows of one 16-lane group, bits 2 and 4 those of one 32-lane
+// group).  One LDS-DMA instruction fills 1 KB: lane l writes 16 bytes at
+// 16 * l, i.e. row l / 4, position l % 4, so it loads chunk (l % 4) ^ swz(row)
+// of its row.  The two waves of a slot copy 32 rows each in two instructions.
+__device__ __forceinline__ int swz(int row)
+{
+    return ((row >> 2) & 1) | ((((row >> 1) ^ (row >> 4)) & 1) << 1);
+}
+
 template <>
-struct Stager<V_CI4_TR> {
-    v4i r[ring_depth<V_CI4_TR>()][2];  // ring: slot k % depth holds step k
+struct Stager<V_CI4_DMA> {
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t vofs[2];
-    int lofs[2];
+    int lds_ofs;
     int row_bytes;
-    int lds_slot;
 
+    // A wave whose slot is unused copies zeros (its range is empty) into that
+    // slot, which no wave reads; every wave thus issues the same loads.
     __device__ __forceinline__ void init(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane)
     {
-        lds_slot = w.stage_rb < 0 ? -1 : w.stage_slot;
         row_bytes = a.row_bytes;
         rsrc = channel_rsrc(a, w.stage_rb, w.stage_ch);
-        const int q = lane & 3;
-        const int r16 = ((lane >> 3) & 3) + 4 * ((lane >> 2) & 1) + 8 * (lane >> 5);
-        const int input = (w.stage_rb < 0 ? 0 : w.stage_rb) * kRowBlock + 16 * q;
+        lds_ofs = w.stage_slot * Geo<V_CI4_DMA>::kSlotBytes + 32 * w.stage_part * kRowBlock;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int row = 32 * w.stage_part + 16 * j + r16;
+            const int row = 32 * w.stage_part + 16 * j + (lane >> 2);
+            const int q = (lane & 3) ^ swz(row);
+            const int input = (w.stage_rb < 0 ? 0 : w.stage_rb) * kRowBlock + 16 * q;
             vofs[j] = (uint32_t)row * (uint32_t)a.row_bytes + column_offset(input, a.n_inputs, 1);
-            lofs[j] = row * kPitch + 16 * q;
         }
     }
 
-    template <int S>
-    __device__ __forceinline__ void load(int k)
+    // Copies the samples of step k into LDS buffer buf (past the chunk: zeros).
+    __device__ __forceinline__ void load(uint8_t* buf, int k) const
     {
+        typedef __attribute__((address_space(3))) void lds_void;
         const uint32_t step = (uint32_t)(k * kStep) * (uint32_t)row_bytes;
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-            r[S][j] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(vofs[j] + step), 0, 0));
-    }
-
-    template <int S>
-    __device__ __forceinline__ void store(uint8_t* buf) const
-    {
-        if (lds_slot < 0) return;
-        uint8_t* slot = buf + lds_slot * Geo<V_CI4_TR>::kSlotBytes;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) *(v4i*)(slot + lofs[j]) = r[S][j];
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void*)(buf + lds_ofs + 16 * kRowBlock * j), 16,
+                                                     (int)(vofs[j] + step), 0, 0, 0);
     }
 };
 
@@ -198,20 +210,31 @@ __device__ __forceinline__ v4i frag(const uint8_t* part, int blk, int lane)
     return *(const v4i*)(part + (16 * blk + (lane & 15)) * kPitch + 16 * (lane >> 4));
 }
 
-// The same fragment from a natural-order slot ([sample][input] rows): within
+// The same fragment from a V_CI4_DMA slot ([sample][input] rows): within
 // each group of 16 lanes, lane j points at 8 bytes (inputs 8*(j%2)..+7 of the
 // block) of sample row j/2, and the transpose read returns to lane L the
 // byte of input L from each of the 8 rows.  Two reads give the 16 samples.
-__device__ __forceinline__ v4i frag_tr(const uint8_t* part, int blk, int lane)
+// ofs is the lane's byte offset of the block within the buffer (tr_offset).
+__device__ __forceinline__ v4i frag_tr(const uint8_t* buf, int ofs)
 {
     typedef int v2i __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) v2i lds_v2i;
-    const int j = lane & 15;
-    const uint8_t* p = part + (16 * (lane >> 4) + (j >> 1)) * kPitch + 16 * blk + 8 * (j & 1);
-    const v2i lo = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i*)(p));
-    const v2i hi = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i*)(p + 8 * kPitch));
+    const v2i lo = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i*)(buf + ofs));
+    const v2i hi = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i*)(buf + ofs + 8 * kRowBlock));
     return v4i{lo.x, lo.y, hi.x, hi.y};
 }
+
+__device__ __forceinline__ int tr_offset(int slot, int blk, int lane)
+{
+    const int j = lane & 15;
+    const int row = 16 * (lane >> 4) + (j >> 1);
+    return slot * Geo<V_CI4_DMA>::kSlotBytes + row * kRowBlock + 16 * (blk ^ swz(row)) + 8 * (j & 1);
+}
+
+// Per-lane fragment offsets of the I and J slots (V_CI4_DMA only).
+struct FragOfs {
+    int i[4], j[4];
+};
 
 // CI4 byte = (re << 4) | (im & 0xF): masking gives 16*re and 16*im as exact int8.
 __device__ __forceinline__ v4i hi16(v4i x)
@@ -244,7 +267,7 @@ struct Raw<V_CI4> {
     v4i ri[4], rj[4];
 };
 template <>
-struct Raw<V_CI4_TR> {
+struct Raw<V_CI4_DMA> {
     v4i ri[4], rj[4];
 };
 template <>
@@ -271,7 +294,8 @@ __device__ __forceinline__ constexpr bool need_j(int b)
 }
 
 template <int FMT, int KIND>
-__device__ __forceinline__ void read_raw(const uint8_t* buf, int si, int sj, int lane, Raw<FMT>& r)
+__device__ __forceinline__ void read_raw(const uint8_t* buf, int si, int sj, int lane, const FragOfs& fo,
+                                         Raw<FMT>& r)
 {
     const uint8_t* pI = buf + si * Geo<FMT>::kSlotBytes;
     const uint8_t* pJ = buf + sj * Geo<FMT>::kSlotBytes;
@@ -280,9 +304,9 @@ __device__ __forceinline__ void read_raw(const uint8_t* buf, int si, int sj, int
         if constexpr (FMT == V_CI4) {
             if (need_i<KIND>(b)) r.ri[b] = frag(pI, b, lane);
             if (need_j<KIND>(b)) r.rj[b] = frag(pJ, b, lane);
-        } else if constexpr (FMT == V_CI4_TR) {
-            if (need_i<KIND>(b)) r.ri[b] = frag_tr(pI, b, lane);
-            if (need_j<KIND>(b)) r.rj[b] = frag_tr(pJ, b, lane);
+        } else if constexpr (FMT == V_CI4_DMA) {
+            if (need_i<KIND>(b)) r.ri[b] = frag_tr(buf, fo.i[b]);
+            if (need_j<KIND>(b)) r.rj[b] = frag_tr(buf, fo.j[b]);
         } else {
             if (need_i<KIND>(b)) {
                 r.o.ia[b] = frag(pI, b, lane);
@@ -354,54 +378,141 @@ __device__ __forceinline__ void mma(const Ops& o, Acc& c)
             }
 }
 
-// Three LDS buffers, step k in buffer k % 3.  CI4 step k: load the samples
-// of step k + kPrefetch into ring slot S = k % kPrefetch, read the raw
-// fragments of step k+1, run the MFMAs of step k from registers, split the
-// step-k+1 fragments into operands, and write step k+2 (ring slot
-// (S+2) % kPrefetch) into buffer (k+2) % 3.  The MFMAs are interleaved with
-// the independent vector work of the next steps.  Buffer (k+2) % 3 last held
-// step k-1, whose fragments were read in step k-2; buffer (k+1) % 3 was
-// written in step k-1.  CI8 fragments are twice as large: they are read at
-// the start of their own step from buffer k % 3.
+// LDS buffers of the pipeline.  V_CI4_DMA gives every buffer its own LDS
+// variable, so that the compiler can tell a copy into one buffer from the
+// fragment reads of another and does not make those reads wait for it.
+// The other variants index one array with a runtime step: p[0] is its base.
+struct Bufs {
+    uint8_t* p[8];
+};
+
+// Waits until at most N of this wave's vector-memory loads are in flight
+// and all of its LDS reads have returned (expcnt left at its maximum).
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm()
+{
+    static_assert(N >= 0 && N < 16, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt(N | (0x7 << 4));
+}
+
+// Workgroup barrier of the LDS-DMA pipeline.  A __syncthreads() fence would
+// wait for every LDS-DMA copy in flight (they count as LDS writes); here the
+// wave waits only for its copies older than the newest N and for its own
+// LDS reads, which is all the next step needs.  The empty asm keeps the
+// compiler from moving memory accesses across the barrier.
+template <int N>
+__device__ __forceinline__ void dma_barrier()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    wait_vm_lgkm<N>();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Issue pattern of one step: global loads, fragment reads, then the MFMAs
+// each followed by a few vector instructions, then the LDS writes.
+template <int FMT, int KIND>
+__device__ __forceinline__ void schedule_step()
+{
+    constexpr int nm = 4 * n_blocks<KIND>();
+    if constexpr (FMT == V_CI4_DMA) {
+        constexpr int n_dsr = 2 * n_frags<KIND>();
+        constexpr int n_valu = 12 * n_frags<KIND>();
+        // The copies and fragment reads are spread over the step so that no
+        // wave stalls behind a burst of them: a few MFMAs, one copy, a few
+        // MFMAs, the other copy, then one fragment read after each of the
+        // next MFMAs, then the splitting work after each of the rest.
+        constexpr int a = nm / 8 > 0 ? nm / 8 : 1;
+        constexpr int rest = nm - 2 * a;
+        constexpr int rm = (rest / 2 < n_dsr ? rest / 2 : n_dsr) > 0 ? (rest / 2 < n_dsr ? rest / 2 : n_dsr) : 1;
+        constexpr int rpm = (n_dsr + rm - 1) / rm;
+        constexpr int vm = rest - rm > 0 ? rest - rm : 1;
+        constexpr int vpm = (n_valu + vm - 1) / vm;
+        __builtin_amdgcn_sched_group_barrier(0x008, a, 0);        // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);        // VMEM (copy)
+        __builtin_amdgcn_sched_group_barrier(0x008, a, 0);
+        __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);
+#pragma unroll
+        for (int m = 0; m < rm; ++m) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, rpm, 0);  // DS read
+        }
+#pragma unroll
+        for (int m = 0; m < vm; ++m) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, vpm, 0);  // VALU
+        }
+    } else {
+        __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);        // VMEM read
+        __builtin_amdgcn_sched_group_barrier(0x100, n_frags<KIND>(), 0);   // DS read
+#pragma unroll
+        for (int m = 0; m < nm; ++m) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);    // VALU
+        }
+        __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);        // DS write
+    }
+}
+
+// V_CI4 and V_CI8: three LDS buffers, step k in buffer k % 3.  CI4 step k:
+// load the samples of step k + kPrefetch into ring slot S = k % kPrefetch,
+// read the raw fragments of step k+1, run the MFMAs of step k from
+// registers, split the step-k+1 fragments into operands, and write step k+2
+// (ring slot (S+2) % kPrefetch) into buffer (k+2) % 3.  The MFMAs are
+// interleaved with the independent vector work of the next steps.  Buffer
+// (k+2) % 3 last held step k-1, whose fragments were read in step k-2;
+// buffer (k+1) % 3 was written in step k-1.  CI8 fragments are twice as
+// large: they are read at the start of their own step from buffer k % 3.
+//
+// V_CI4_DMA: kDmaDepth buffers, step k in buffer S = k % kDmaDepth.  Step k
+// reads the fragments of step k+1, then refills buffer S (whose fragments,
+// step k's, were read in step k-1) with step k + kDmaDepth, runs the MFMAs
+// of step k and, before the barrier, waits for its own copy of step k+2: the
+// copies of the kDmaDepth - 2 later steps may stay in flight.
 template <int FMT, int KIND, int S>
-__device__ __forceinline__ void pipeline_step(int k, Stager<FMT>& st, uint8_t* lds, int si, int sj,
-                                              int lane, Ops& ops, Acc& c)
+__device__ __forceinline__ void pipeline_step(int k, Stager<FMT>& st, const Bufs& L, int si, int sj,
+                                              int lane, const FragOfs& fo, Ops& ops, Acc& c)
 {
     constexpr int B = Geo<FMT>::kBufBytes;
-    uint8_t* next = lds + ((k + 1) % 3) * B;
-    uint8_t* after = lds + ((k + 2) % 3) * B;
-    constexpr int D = ring_depth<FMT>();
-    st.template load<S % D>(k + D);
-    if constexpr (is_ci4(FMT)) {
+    uint8_t* lds = L.p[0];
+    if constexpr (FMT == V_CI4_DMA) {
+        constexpr int D = kDmaDepth;
+        st.load(L.p[S], k + D);
+        Ops nx;
+        if constexpr (KIND != KIND_NONE) {
+            Raw<FMT> raw;
+            read_raw<FMT, KIND>(L.p[(S + 1) % D], si, sj, lane, fo, raw);
+            mma<KIND>(ops, c);
+            prepare<FMT, KIND>(raw, nx);
+            schedule_step<FMT, KIND>();
+        }
+        dma_barrier<2 * (D - 2)>();
+        ops = nx;
+    } else if constexpr (is_ci4(FMT)) {
+        constexpr int D = ring_depth<FMT>();
+        uint8_t* next = lds + ((k + 1) % 3) * B;
+        uint8_t* after = lds + ((k + 2) % 3) * B;
+        st.template load<S % D>(k + D);
         Raw<FMT> raw;
         Ops nx;
         if (KIND != KIND_NONE) {
-            read_raw<FMT, KIND>(next, si, sj, lane, raw);
+            read_raw<FMT, KIND>(next, si, sj, lane, fo, raw);
             mma<KIND>(ops, c);
             prepare<FMT, KIND>(raw, nx);
         }
         st.template store<(S + 2) % D>(after);
-        if (KIND != KIND_NONE) {
-            // issue order: global loads, fragment reads, then MFMAs each
-            // followed by a few vector instructions, then the LDS writes
-            constexpr int nm = 4 * n_blocks<KIND>();
-            constexpr int n_vmem = FMT == V_CI4_TR ? 2 : 8;
-            constexpr int n_dsr = n_frags<KIND>() * (FMT == V_CI4_TR ? 2 : 1);
-            __builtin_amdgcn_sched_group_barrier(0x020, n_vmem, 0);   // VMEM read
-            __builtin_amdgcn_sched_group_barrier(0x100, n_dsr, 0);    // DS read
-#pragma unroll
-            for (int m = 0; m < nm; ++m) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
-                __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);    // VALU
-            }
-            __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);        // DS write
-        }
+        if (KIND != KIND_NONE) schedule_step<FMT, KIND>();
         __syncthreads();
         ops = nx;
     } else {
+        constexpr int D = ring_depth<FMT>();
+        uint8_t* after = lds + ((k + 2) % 3) * B;
+        st.template load<S % D>(k + D);
         if (KIND != KIND_NONE) {
             Raw<FMT> raw;
-            read_raw<FMT, KIND>(lds + (k % 3) * B, si, sj, lane, raw);
+            read_raw<FMT, KIND>(lds + (k % 3) * B, si, sj, lane, fo, raw);
             prepare<FMT, KIND>(raw, ops);
             mma<KIND>(ops, c);
         }
@@ -411,10 +522,19 @@ __device__ __forceinline__ void pipeline_step(int k, Stager<FMT>& st, uint8_t* l
     }
 }
 
+template <int FMT, int KIND, int... S>
+__device__ __forceinline__ void pipeline_group(int k0, Stager<FMT>& st, const Bufs& L, int si, int sj, int lane,
+                                               const FragOfs& fo, Ops& ops, Acc& c,
+                                               std::integer_sequence<int, S...>)
+{
+    (pipeline_step<FMT, KIND, S>(k0 + S, st, L, si, sj, lane, fo, ops, c), ...);
+}
+
 template <int FMT, int KIND>
 __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane,
-                                         uint8_t* lds)
+                                         const Bufs& L)
 {
+    uint8_t* lds = L.p[0];
     Stager<FMT> st;
     st.init(a, w, lane);
     const int nk = (a.t_len + kStep - 1) / kStep;
@@ -430,36 +550,55 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
             c.ba[bi][bj] = v4i{0, 0, 0, 0};
         }
     const int si = w.si, sj = w.sj;
+    FragOfs fo;
+    if constexpr (FMT == V_CI4_DMA) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            fo.i[b] = tr_offset(si, b, lane);
+            fo.j[b] = tr_offset(sj, b, lane);
+        }
+    }
 
-    // Prologue: samples of steps 0..kPrefetch-1 into the ring, steps 0 and 1
-    // into LDS buffers 0 and 1, operands of step 0.  Loads past the window
-    // read zeros, and a step past it multiplies zeros, so the steps run in
-    // unconditional groups of kPrefetch; the compiler can then count the
-    // loads in flight across the loop back-edge and waits only for the
-    // oldest group.
-    static_assert(kPrefetch == 4, "the unrolled ring below assumes four slots");
-    constexpr int D = ring_depth<FMT>();
-    st.template load<0>(0);
-    st.template load<1 % D>(1);
-    if (D == 4) {
-        st.template load<2 % D>(2);
-        st.template load<3 % D>(3);
-    }
-    st.template store<0>(lds);
-    st.template store<1 % D>(lds + Geo<FMT>::kBufBytes);
-    __syncthreads();
+    // Prologue.  Loads past the window read zeros, and a step past it
+    // multiplies zeros, so the steps run in unconditional groups; the
+    // compiler can then count the loads in flight across the loop back-edge.
+    constexpr int G = group_steps<FMT>();
     Ops ops;
-    if (is_ci4(FMT) && KIND != KIND_NONE) {
-        Raw<FMT> raw;
-        read_raw<FMT, KIND>(lds, si, sj, lane, raw);
-        prepare<FMT, KIND>(raw, ops);
+    if constexpr (FMT == V_CI4_DMA) {
+        // Copies of steps 0..D-1 into buffers 0..D-1, operands of step 0;
+        // the second barrier frees buffer 0 and publishes step 1.
+        constexpr int D = kDmaDepth;
+#pragma unroll
+        for (int s = 0; s < D; ++s) st.load(L.p[s], s);
+        dma_barrier<2 * (D - 1)>();
+        if (KIND != KIND_NONE) {
+            Raw<FMT> raw;
+            read_raw<FMT, KIND>(lds, si, sj, lane, fo, raw);
+            prepare<FMT, KIND>(raw, ops);
+        }
+        dma_barrier<2 * (D - 2)>();
+    } else {
+        // Samples of steps 0..kPrefetch-1 into the ring, steps 0 and 1 into
+        // LDS buffers 0 and 1, operands of step 0 (CI4).
+        static_assert(kPrefetch == 4, "the unrolled ring below assumes four slots");
+        st.template load<0>(0);
+        st.template load<1>(1);
+        st.template load<2>(2);
+        st.template load<3>(3);
+        st.template store<0>(lds);
+        st.template store<1>(lds + Geo<FMT>::kBufBytes);
+        __syncthreads();
+        if (is_ci4(FMT) && KIND != KIND_NONE) {
+            Raw<FMT> raw;
+            read_raw<FMT, KIND>(lds, si, sj, lane, fo, raw);
+            prepare<FMT, KIND>(raw, ops);
+        }
     }
-    for (int k0 = 0; k0 < nk; k0 += kPrefetch) {
-        pipeline_step<FMT, KIND, 0>(k0 + 0, st, lds, si, sj, lane, ops, c);
-        pipeline_step<FMT, KIND, 1>(k0 + 1, st, lds, si, sj, lane, ops, c);
-        pipeline_step<FMT, KIND, 2>(k0 + 2, st, lds, si, sj, lane, ops, c);
-        pipeline_step<FMT, KIND, 3>(k0 + 3, st, lds, si, sj, lane, ops, c);
-    }
+    for (int k0 = 0; k0 < nk; k0 += G)
+        pipeline_group<FMT, KIND>(k0, st, L, si, sj, lane, fo, ops, c, std::make_integer_sequence<int, G>());
+    // The copies issued by the last steps (zeros past the window) land
+    // before the wave moves on.
+    if constexpr (FMT == V_CI4_DMA) wait_vm_lgkm<0>();
     if (KIND == KIND_NONE) return;
 
     // Epilogue: 16x16 int32 result blocks hold column (lane % 16) and rows
@@ -500,21 +639,32 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
 template <int FMT>
 __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_kernel(LaunchArgs a)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[3 * Geo<FMT>::kBufBytes];
+    constexpr int B = Geo<FMT>::kBufBytes;
+    Bufs L;
+    if constexpr (FMT == V_CI4_DMA) {
+        __shared__ __attribute__((aligned(16))) uint8_t b0[B], b1[B], b2[B], b3[B], b4[B], b5[B], b6[B], b7[B];
+        uint8_t* const all[8] = {b0, b1, b2, b3, b4, b5, b6, b7};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) L.p[i] = i < kDmaDepth ? all[i] : nullptr;
+    } else {
+        __shared__ __attribute__((aligned(16))) uint8_t lds[3 * B];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) L.p[i] = i < 3 ? lds + i * B : nullptr;
+    }
     const int b = work_item_index(blockIdx.x, a.n_blocks, a.xcd_map);
     if (b >= a.n_blocks) return;
     const WaveJobT<kWaves> w = wave_job<kWaves>(a, b);
     const int lane = threadIdx.x & 63;
     switch (w.kind) {
-    case KIND_HALF0:  run_tile<FMT, KIND_HALF0>(a, w, lane, lds); break;
-    case KIND_HALF1:  run_tile<FMT, KIND_HALF1>(a, w, lane, lds); break;
-    case KIND_DIAG_A: run_tile<FMT, KIND_DIAG_A>(a, w, lane, lds); break;
-    case KIND_DIAG_B: run_tile<FMT, KIND_DIAG_B>(a, w, lane, lds); break;
-    case KIND_QUART0: run_tile<FMT, KIND_QUART0>(a, w, lane, lds); break;
-    case KIND_QUART1: run_tile<FMT, KIND_QUART1>(a, w, lane, lds); break;
-    case KIND_QUART2: run_tile<FMT, KIND_QUART2>(a, w, lane, lds); break;
-    case KIND_QUART3: run_tile<FMT, KIND_QUART3>(a, w, lane, lds); break;
-    default:          run_tile<FMT, KIND_NONE>(a, w, lane, lds); break;
+    case KIND_HALF0:  run_tile<FMT, KIND_HALF0>(a, w, lane, L); break;
+    case KIND_HALF1:  run_tile<FMT, KIND_HALF1>(a, w, lane, L); break;
+    case KIND_DIAG_A: run_tile<FMT, KIND_DIAG_A>(a, w, lane, L); break;
+    case KIND_DIAG_B: run_tile<FMT, KIND_DIAG_B>(a, w, lane, L); break;
+    case KIND_QUART0: run_tile<FMT, KIND_QUART0>(a, w, lane, L); break;
+    case KIND_QUART1: run_tile<FMT, KIND_QUART1>(a, w, lane, L); break;
+    case KIND_QUART2: run_tile<FMT, KIND_QUART2>(a, w, lane, L); break;
+    case KIND_QUART3: run_tile<FMT, KIND_QUART3>(a, w, lane, L); break;
+    default:          run_tile<FMT, KIND_NONE>(a, w, lane, L); break;
     }
 }
 
@@ -524,7 +674,7 @@ hipError_t launch_i8(const LaunchArgs& a, int fmt, hipStream_t s)
 {
     const dim3 grid(launch_blocks(a.n_blocks, a.xcd_map)), block(kThreads);
     if (fmt == 1)                  hipLaunchKernelGGL(xcorr_i8_kernel<V_CI8>, grid, block, 0, s, a);
-    else if (a.n_inputs % 16 == 0) hipLaunchKernelGGL(xcorr_i8_kernel<V_CI4_TR>, grid, block, 0, s, a);
+    else if (a.n_inputs % 16 == 0) hipLaunchKernelGGL(xcorr_i8_kernel<V_CI4_DMA>, grid, block, 0, s, a);
     else                           hipLaunchKernelGGL(xcorr_i8_kernel<V_CI4>, grid, block, 0, s, a);
     return hipGetLastError();
 }
