@@ -67,6 +67,14 @@ typedef enum {
 /* Plan flags. */
 #define XCORR_FLAG_NO_XCD_MAP 0x2u /* dispatch work items in plain order (for tests)  */
 
+/* Tile variants of the int8 path (xcorr_plan_desc.tile).  All give identical
+ * (exact) results; they differ in how samples reach LDS.  The LDS-DMA variants
+ * need XCORR_CI4 and n_inputs % 16 == 0. */
+#define XCORR_TILE_DEFAULT 0       /* LDS-DMA depth 8 where allowed, else registers */
+#define XCORR_TILE_DMA8 1          /* buffer loads straight to LDS, 8 steps in flight */
+#define XCORR_TILE_DMA4 2          /* the same, 4 steps in flight                   */
+#define XCORR_TILE_REGS 3          /* loads to registers, byte transposes, LDS writes */
+
 typedef struct xcorr_plan_s* xcorr_plan_t;
 
 typedef struct {
@@ -76,7 +84,7 @@ typedef struct {
     int32_t path;                /* xcorr_path                                        */
     void* stream;                /* hipStream_t, NULL = the null stream               */
     uint32_t flags;              /* XCORR_FLAG_*                                      */
-    int32_t tile;                /* 0 = tuned default; else a tile variant id         */
+    int32_t tile;                /* XCORR_TILE_*; 0 = default                         */
 } xcorr_plan_desc;
 
 typedef struct {
@@ -125,6 +133,60 @@ xcorr_status xcorr_plan_bytes(const xcorr_plan_desc* desc, size_t* bytes);
 
 /* Release the plan (waits for its stream).  Destroying NULL is XCORR_ERR_STATE. */
 xcorr_status xcorr_destroy(xcorr_plan_t plan);
+
+/* ------------------------------------------------------------------------
+ * Batches: several plans (subarrays of uneven input and channel counts, the
+ * X-stage of several arrays sharing one GPU, Sec. 3) run as ONE persistent
+ * launch per time chunk.  Every plan of a batch must use XCORR_PATH_I8_MFMA
+ * and the same format.  The batch borrows the plans: they must outlive it,
+ * and while the batch is in use they must not be used on their own streams.
+ * ------------------------------------------------------------------------ */
+typedef struct xcorr_batch_s* xcorr_batch_t;
+
+typedef struct {
+    int32_t tile;                /* XCORR_TILE_* used for every plan of the batch    */
+    int32_t grid;                /* persistent workgroups (multiple of 8)            */
+    int32_t balance;             /* 1: XCD slices of equal cost; 0: equal item counts */
+    int32_t reserved;
+} xcorr_batch_config;
+
+/* Create a batch over n_plans (1..64) plans; work is enqueued on `stream`
+ * (hipStream_t, NULL = null stream).  Starts from the default configuration. */
+xcorr_status xcorr_batch_create(xcorr_batch_t* out, const xcorr_plan_t* plans, int32_t n_plans,
+                                void* stream);
+
+/* One step for every plan k of the batch, in one launch per time chunk:
+ * n_time[k] samples of d_in[k] (layout of xcorr_accumulate) are added to plan
+ * k's integration; if d_out[k] is non-NULL the plan is then dumped to d_out[k]
+ * (layout of xcorr_dump), restarting the integration if reset[k] != 0.
+ * n_time[k] == 0 with d_out[k] == NULL leaves plan k untouched.  reset and
+ * info may be NULL (no reset; no info); info[k] is filled for dumped plans. */
+xcorr_status xcorr_batch_run(xcorr_batch_t batch, const void* const* d_in, const int64_t* n_time,
+                             void* const* d_out, const int32_t* reset, xcorr_dump_info* info);
+
+xcorr_status xcorr_batch_get_config(xcorr_batch_t batch, xcorr_batch_config* config);
+xcorr_status xcorr_batch_set_config(xcorr_batch_t batch, const xcorr_batch_config* config);
+
+/* Autotuner: times every candidate configuration (tile x grid x balance) on
+ * `reps` windows of the given inputs (every plan must be freshly reset; the
+ * windows are not kept) and keeps the fastest.  chosen and ms_best may be
+ * NULL.  Synchronises the batch stream. */
+xcorr_status xcorr_batch_autotune(xcorr_batch_t batch, const void* const* d_in, const int64_t* n_time,
+                                  int32_t reps, xcorr_batch_config* chosen, float* ms_best);
+
+/* Graphs: capture one integration step of the batch -- every plan k takes
+ * n_time[k] > 0 samples from d_in[k] and is dumped with reset to d_out[k] --
+ * as a hipGraph, and replay it.  Pointers and sizes are fixed at capture;
+ * each replay is one full window per plan (plans must be freshly reset at
+ * capture time and used only through the graph while it exists). */
+typedef struct xcorr_graph_s* xcorr_graph_t;
+xcorr_status xcorr_batch_capture(xcorr_batch_t batch, const void* const* d_in, const int64_t* n_time,
+                                 void* const* d_out, xcorr_graph_t* graph);
+xcorr_status xcorr_graph_launch(xcorr_graph_t graph);
+xcorr_status xcorr_graph_destroy(xcorr_graph_t graph);
+
+/* Release the batch (waits for its stream); the plans stay valid. */
+xcorr_status xcorr_batch_destroy(xcorr_batch_t batch);
 
 const char* xcorr_strerror(xcorr_status status);
 const char* xcorr_last_error(void);

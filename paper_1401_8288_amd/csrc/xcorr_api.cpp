@@ -1,7 +1,6 @@
 // Host side of libxcorr: argument checking, plan state, work decomposition
 // and the launch sequence of accumulate / dump.  See include/xcorr.h.
-#include "xcorr.h"
-#include "xcorr_internal.h"
+#include "xcorr_host.h"
 
 #include <algorithm>
 #include <cstdarg>
@@ -15,33 +14,14 @@
 
 using namespace xcorr;
 
-struct xcorr_plan_s {
-    xcorr_plan_desc d;
-    int device = 0;
-    hipStream_t stream = nullptr;
-    int64_t n_b = 0;                // baselines per channel
-    size_t out_bytes = 0;
-    void* acc = nullptr;            // accumulator, same layout as a dump
-    bool acc_valid = false;         // false: accumulator is logically zero
-    WorkItem* d_items = nullptr;
-    int n_items = 0;                // items per channel group
-    int ch_group = 1;
-    int n_groups = 0;
-    int xcd_map = 1;
-    int64_t fold_bound = 0;
-    int64_t samples = 0;            // samples since the last reset
-    int64_t window_start = 0;       // absolute sample index of the current window
-    int64_t total = 0;              // absolute samples accumulated
-    int64_t n_dumps = 0;
-};
-
 namespace {
-
 thread_local std::string g_err;
 std::mutex g_mu;
 std::set<xcorr_plan_t> g_live;
+}  // namespace
 
-xcorr_status fail(xcorr_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+namespace xcorr {
+
 xcorr_status fail(xcorr_status s, const char* fmt, ...)
 {
     char buf[512];
@@ -58,16 +38,71 @@ xcorr_status hip_fail(hipError_t e, const char* what)
     return fail(XCORR_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+bool plan_live(xcorr_plan_t p)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return p != nullptr && g_live.count(p) != 0;
+}
+
+xcorr_status check_ptr(const void* ptr, const char* name)
+{
+    if (!ptr) return fail(XCORR_ERR_ARG, "%s is null", name);
+    if ((uintptr_t)ptr % 16) return fail(XCORR_ERR_ARG, "%s is not 16-byte aligned", name);
+    return XCORR_OK;
+}
+
+int64_t row_bytes_of(const xcorr_plan_s* p)
+{
+    return (int64_t)p->d.n_inputs * (p->d.format == XCORR_CI4 ? 1 : 2);
+}
+
+LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
+                      const void* src, void* dst)
+{
+    LaunchArgs a;
+    a.in = in;
+    a.chan_stride = chan_stride;
+    a.row_bytes = (int32_t)row_bytes_of(p);
+    a.n_inputs = p->d.n_inputs;
+    a.t_len = t_len;
+    a.n_channels = p->d.n_channels;
+    a.ch_group = p->ch_group;
+    a.n_items = p->n_items;
+    a.n_blocks = p->n_items * p->n_groups;
+    a.xcd_map = p->xcd_map;
+    a.items = p->d_items;
+    a.src = src;
+    a.dst = dst;
+    return a;
+}
+
+void fill_info(const xcorr_plan_s* p, xcorr_dump_info* info)
+{
+    if (!info) return;
+    info->samples_accumulated = p->samples;
+    info->start_sample = p->window_start;
+    info->n_dumps = p->n_dumps;
+}
+
+int item_blocks(const WorkItem& it)
+{
+    int n = 0;
+    for (int w = 0; w < kMaxWaves; ++w) n += __builtin_popcount(kind_mask(it.kind[w]));
+    return n;
+}
+
+}  // namespace xcorr
+
+namespace {
+
+using namespace xcorr;
+
 void release(void* ptr)
 {
     if (ptr) (void)hipFree(ptr);
 }
 
-bool live(xcorr_plan_t p)
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    return p != nullptr && g_live.count(p) != 0;
-}
+bool live(xcorr_plan_t p) { return plan_live(p); }
 
 WorkItem blank_item()
 {
@@ -229,7 +264,11 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
                     align);
     if (d->flags & ~XCORR_FLAG_NO_XCD_MAP)
         return fail(XCORR_ERR_ARG, "unknown flags 0x%x", d->flags);
-    if (d->tile != 0) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
+    if (d->tile < 0 || d->tile > kTileRegs) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
+    if (d->tile != kTileDefault && d->path != XCORR_PATH_I8_MFMA)
+        return fail(XCORR_ERR_UNSUPPORTED, "tile variants exist for the int8 path only");
+    if ((d->tile == kTileDma8 || d->tile == kTileDma4) && (d->format != XCORR_CI4 || d->n_inputs % 16))
+        return fail(XCORR_ERR_UNSUPPORTED, "LDS-DMA tiles need 4-bit samples and n_inputs %% 16 == 0");
     return XCORR_OK;
 }
 
@@ -242,23 +281,10 @@ size_t plan_device_bytes(const xcorr_plan_desc* d, size_t n_items)
 xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
                           const void* src, void* dst)
 {
-    LaunchArgs a;
-    a.in = in;
-    a.chan_stride = chan_stride;
-    a.row_bytes = p->d.n_inputs * (p->d.format == XCORR_CI4 ? 1 : 2);
-    a.n_inputs = p->d.n_inputs;
-    a.t_len = t_len;
-    a.n_channels = p->d.n_channels;
-    a.ch_group = p->ch_group;
-    a.n_items = p->n_items;
-    a.n_blocks = p->n_items * p->n_groups;
-    a.xcd_map = p->xcd_map;
-    a.items = p->d_items;
-    a.src = src;
-    a.dst = dst;
+    const LaunchArgs a = chunk_args(p, in, chan_stride, t_len, src, dst);
     hipError_t e;
     switch (p->d.path) {
-    case XCORR_PATH_I8_MFMA: e = launch_i8(a, p->d.format, p->stream); break;
+    case XCORR_PATH_I8_MFMA: e = launch_i8(a, p->d.format, p->tile, p->stream); break;
     case XCORR_PATH_F16_MFMA: e = launch_f16(a, p->d.format, p->stream); break;
     default: e = launch_f32(a, p->d.format, p->stream); break;
     }
@@ -266,18 +292,11 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
     return XCORR_OK;
 }
 
-xcorr_status check_ptr(const void* ptr, const char* name)
-{
-    if (!ptr) return fail(XCORR_ERR_ARG, "%s is null", name);
-    if ((uintptr_t)ptr % 16) return fail(XCORR_ERR_ARG, "%s is not 16-byte aligned", name);
-    return XCORR_OK;
-}
-
 // Runs the launches of one window.  If `final_dst` is non-null the last chunk
 // writes its result there instead of into the accumulator.
 xcorr_status run_window(xcorr_plan_t p, const void* d_in, int64_t n_time, void* final_dst)
 {
-    const int64_t row = (int64_t)p->d.n_inputs * (p->d.format == XCORR_CI4 ? 1 : 2);
+    const int64_t row = row_bytes_of(p);
     const int64_t chan_stride = row * n_time;
     const uint8_t* in = (const uint8_t*)d_in;
     for (int64_t t0 = 0; t0 < n_time; t0 += p->fold_bound) {
@@ -290,14 +309,6 @@ xcorr_status run_window(xcorr_plan_t p, const void* d_in, int64_t n_time, void* 
         if (dst == p->acc) p->acc_valid = true;
     }
     return XCORR_OK;
-}
-
-void fill_info(xcorr_plan_t p, xcorr_dump_info* info)
-{
-    if (!info) return;
-    info->samples_accumulated = p->samples;
-    info->start_sample = p->window_start;
-    info->n_dumps = p->n_dumps;
 }
 
 }  // namespace
@@ -364,7 +375,8 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
     const int64_t row = (int64_t)d->n_inputs * (d->format == XCORR_CI4 ? 1 : 2);
     p->fold_bound = std::min<int64_t>(p->fold_bound, ((int64_t)1 << 31) / row - 1);
 
-    std::vector<WorkItem> items;
+    p->tile = d->tile;
+    std::vector<WorkItem>& items = p->h_items;
     plan_items(d->path, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, p->ch_group);
     p->n_items = (int)items.size();
     p->n_groups = (d->n_channels + p->ch_group - 1) / p->ch_group;
@@ -472,7 +484,7 @@ xcorr_status xcorr_query(xcorr_plan_t p, xcorr_plan_info* info)
     info->input_bytes_per_sample =
         (size_t)p->d.n_inputs * (p->d.format == XCORR_CI4 ? 1 : 2) * p->d.n_channels;
     info->fold_bound = p->fold_bound;
-    info->tile = 0;
+    info->tile = p->tile;
     info->work_items = p->n_items * p->n_groups;
     info->items_per_group = p->n_items;
     info->channels_per_group = p->ch_group;

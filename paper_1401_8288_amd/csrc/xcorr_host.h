@@ -1,0 +1,46 @@
+// Host-side state shared by the plan API (xcorr_api.cpp), the batch API
+// (xcorr_batch.cpp) and the server (xcorr_server.cpp).
+#pragma once
+
+#include "xcorr.h"
+#include "xcorr_internal.h"
+
+#include <vector>
+
+struct xcorr_plan_s {
+    xcorr_plan_desc d;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n_b = 0;                // baselines per channel
+    size_t out_bytes = 0;
+    void* acc = nullptr;            // accumulator, same layout as a dump
+    bool acc_valid = false;         // false: accumulator is logically zero
+    xcorr::WorkItem* d_items = nullptr;
+    std::vector<xcorr::WorkItem> h_items;
+    int n_items = 0;                // items per channel group
+    int ch_group = 1;
+    int n_groups = 0;
+    int xcd_map = 1;
+    int tile = 0;                   // int8 tile variant in use
+    int64_t fold_bound = 0;
+    int64_t samples = 0;            // samples since the last reset
+    int64_t window_start = 0;       // absolute sample index of the current window
+    int64_t total = 0;              // absolute samples accumulated
+    int64_t n_dumps = 0;
+};
+
+namespace xcorr {
+
+xcorr_status fail(xcorr_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+xcorr_status hip_fail(hipError_t e, const char* what);
+bool plan_live(xcorr_plan_t p);
+xcorr_status check_ptr(const void* ptr, const char* name);
+int64_t row_bytes_of(const xcorr_plan_s* p);
+// Launch arguments of one time chunk of a plan.
+LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
+                      const void* src, void* dst);
+void fill_info(const xcorr_plan_s* p, xcorr_dump_info* info);
+// Relative cost of a work item (MFMA blocks its waves own).
+int item_blocks(const WorkItem& it);
+
+}  // namespace xcorr

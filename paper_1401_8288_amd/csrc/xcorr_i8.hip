@@ -41,41 +41,42 @@ constexpr int kWaves = kWavesI8;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kStep = 64;                  // samples per LDS stage
 constexpr int kPitch = 80;                 // LDS bytes per row (64 samples + 16 pad)
-// Global loads run this many steps ahead of the step they feed: a channel's
-// first reader waits for HBM, and the other workgroups of the channel, which
-// run at the same time on the same XCD, wait for the same lines.
+
 // Kernel variants.  V_CI4: 4-bit samples, staged transposed ([input][time]
 // rows) by byte permutes in registers.  V_CI8: 8-bit samples, the same with
-// separate re and im rows.  V_CI4_DMA: 4-bit samples with n_inputs % 16 == 0,
+// separate re and im rows.  V_CI4_DMA*: 4-bit samples with n_inputs % 16 == 0,
 // copied by the buffer unit straight from HBM into LDS in their natural
 // [time][input] order and transposed by the LDS transpose read
 // (ds_read_b64_tr_b8); no vector registers or LDS writes are spent on staging.
-enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_DMA = 2 };
+// The DMA variant comes in two copy-pipeline depths (LDS buffers in flight),
+// 4 and 8; the plan's tile setting or the autotuner picks one.
+enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_DMA4 = 2, V_CI4_DMA8 = 3 };
 __device__ __forceinline__ constexpr bool is_ci4(int v) { return v != V_CI8; }
+__device__ __forceinline__ constexpr bool is_dma(int v) { return v == V_CI4_DMA4 || v == V_CI4_DMA8; }
+__device__ __forceinline__ constexpr int dma_depth(int v) { return v == V_CI4_DMA8 ? 8 : 4; }
 
+// Register-staged variants: global loads run kPrefetch steps ahead of the
+// step they feed: a channel's first reader waits for HBM, and the other
+// workgroups of the channel, which run at the same time on the same XCD, wait
+// for the same lines.
 constexpr int kPrefetch = 4;
-#ifndef XCORR_DMA_DEPTH
-#define XCORR_DMA_DEPTH 8
-#endif
-// V_CI4_DMA: LDS buffers, one per step in flight; the copy of step k + depth
+// V_CI4_DMA*: LDS buffers, one per step in flight; the copy of step k + depth
 // is issued while step k runs.
-constexpr int kDmaDepth = XCORR_DMA_DEPTH;
-static_assert(kDmaDepth >= 3 && kDmaDepth <= 8, "DMA depth");
 template <int FMT>
 __device__ __forceinline__ constexpr int ring_depth() { return kPrefetch; }
 template <int FMT>
-__device__ __forceinline__ constexpr int n_buffers() { return FMT == V_CI4_DMA ? kDmaDepth : 3; }
+__device__ __forceinline__ constexpr int n_buffers() { return is_dma(FMT) ? dma_depth(FMT) : 3; }
 // Steps per unrolled loop iteration.
 template <int FMT>
-__device__ __forceinline__ constexpr int group_steps() { return FMT == V_CI4_DMA ? kDmaDepth : kPrefetch; }
+__device__ __forceinline__ constexpr int group_steps() { return is_dma(FMT) ? dma_depth(FMT) : kPrefetch; }
 
 // LDS geometry.  CI4: one part per slot, the raw bytes (re and im nibbles)
 // of 64 samples x 64 inputs, rows of 64 bytes padded to kPitch.  CI8: two
-// parts, re rows and im rows.  V_CI4_DMA: unpadded 64-byte sample rows.
+// parts, re rows and im rows.  V_CI4_DMA*: unpadded 64-byte sample rows.
 template <int FMT>
 struct Geo {
     static constexpr int kParts = FMT == V_CI8 ? 2 : 1;
-    static constexpr int kRowPitch = FMT == V_CI4_DMA ? kRowBlock : kPitch;
+    static constexpr int kRowPitch = is_dma(FMT) ? kRowBlock : kPitch;
     static constexpr int kPart = kRowBlock * kRowPitch;
     static constexpr int kSlotBytes = kParts * kPart;
     static constexpr int kBufBytes = kSlots * kSlotBytes;
@@ -155,7 +156,7 @@ struct Stager {
     }
 };
 
-// V_CI4_DMA staging.  A slot holds 64 sample rows of 64 bytes; 16-byte chunk
+// V_CI4_DMA* staging.  A slot holds 64 sample rows of 64 bytes; 16-byte chunk
 // q of row r sits at position q ^ swz(r).  The swizzle spreads the rows that
 // one transpose read touches over all LDS banks (bits 1 and 2 of the row
 // separate the rows of one 16-lane group, bits 2 and 4 those of one 32-lane
@@ -167,8 +168,7 @@ __device__ __forceinline__ int swz(int row)
     return ((row >> 2) & 1) | ((((row >> 1) ^ (row >> 4)) & 1) << 1);
 }
 
-template <>
-struct Stager<V_CI4_DMA> {
+struct DmaStager {
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t vofs[2];
     int lds_ofs;
@@ -180,7 +180,7 @@ struct Stager<V_CI4_DMA> {
     {
         row_bytes = a.row_bytes;
         rsrc = channel_rsrc(a, w.stage_rb, w.stage_ch);
-        lds_ofs = w.stage_slot * Geo<V_CI4_DMA>::kSlotBytes + 32 * w.stage_part * kRowBlock;
+        lds_ofs = w.stage_slot * Geo<V_CI4_DMA8>::kSlotBytes + 32 * w.stage_part * kRowBlock;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int row = 32 * w.stage_part + 16 * j + (lane >> 2);
@@ -201,6 +201,10 @@ struct Stager<V_CI4_DMA> {
                                                      (int)(vofs[j] + step), 0, 0, 0);
     }
 };
+template <>
+struct Stager<V_CI4_DMA4> : DmaStager {};
+template <>
+struct Stager<V_CI4_DMA8> : DmaStager {};
 
 // Operand fragment of a 16-row block: lane l holds row l % 16 and the 16
 // samples 16 * (l / 16)..+15 of the step (the same sample set for the A and
@@ -210,7 +214,7 @@ __device__ __forceinline__ v4i frag(const uint8_t* part, int blk, int lane)
     return *(const v4i*)(part + (16 * blk + (lane & 15)) * kPitch + 16 * (lane >> 4));
 }
 
-// The same fragment from a V_CI4_DMA slot ([sample][input] rows): within
+// The same fragment from a V_CI4_DMA* slot ([sample][input] rows): within
 // each group of 16 lanes, lane j points at 8 bytes (inputs 8*(j%2)..+7 of the
 // block) of sample row j/2, and the transpose read returns to lane L the
 // byte of input L from each of the 8 rows.  Two reads give the 16 samples.
@@ -228,10 +232,10 @@ __device__ __forceinline__ int tr_offset(int slot, int blk, int lane)
 {
     const int j = lane & 15;
     const int row = 16 * (lane >> 4) + (j >> 1);
-    return slot * Geo<V_CI4_DMA>::kSlotBytes + row * kRowBlock + 16 * (blk ^ swz(row)) + 8 * (j & 1);
+    return slot * Geo<V_CI4_DMA8>::kSlotBytes + row * kRowBlock + 16 * (blk ^ swz(row)) + 8 * (j & 1);
 }
 
-// Per-lane fragment offsets of the I and J slots (V_CI4_DMA only).
+// Per-lane fragment offsets of the I and J slots (V_CI4_DMA* only).
 struct FragOfs {
     int i[4], j[4];
 };
@@ -267,7 +271,11 @@ struct Raw<V_CI4> {
     v4i ri[4], rj[4];
 };
 template <>
-struct Raw<V_CI4_DMA> {
+struct Raw<V_CI4_DMA4> {
+    v4i ri[4], rj[4];
+};
+template <>
+struct Raw<V_CI4_DMA8> {
     v4i ri[4], rj[4];
 };
 template <>
@@ -304,7 +312,7 @@ __device__ __forceinline__ void read_raw(const uint8_t* buf, int si, int sj, int
         if constexpr (FMT == V_CI4) {
             if (need_i<KIND>(b)) r.ri[b] = frag(pI, b, lane);
             if (need_j<KIND>(b)) r.rj[b] = frag(pJ, b, lane);
-        } else if constexpr (FMT == V_CI4_DMA) {
+        } else if constexpr (is_dma(FMT)) {
             if (need_i<KIND>(b)) r.ri[b] = frag_tr(buf, fo.i[b]);
             if (need_j<KIND>(b)) r.rj[b] = frag_tr(buf, fo.j[b]);
         } else {
@@ -378,7 +386,7 @@ __device__ __forceinline__ void mma(const Ops& o, Acc& c)
             }
 }
 
-// LDS buffers of the pipeline.  V_CI4_DMA gives every buffer its own LDS
+// LDS buffers of the pipeline.  V_CI4_DMA* gives every buffer its own LDS
 // variable, so that the compiler can tell a copy into one buffer from the
 // fragment reads of another and does not make those reads wait for it.
 // The other variants index one array with a runtime step: p[0] is its base.
@@ -417,7 +425,7 @@ template <int FMT, int KIND>
 __device__ __forceinline__ void schedule_step()
 {
     constexpr int nm = 4 * n_blocks<KIND>();
-    if constexpr (FMT == V_CI4_DMA) {
+    if constexpr (is_dma(FMT)) {
         constexpr int n_dsr = 2 * n_frags<KIND>();
         constexpr int n_valu = 12 * n_frags<KIND>();
         // The copies and fragment reads are spread over the step so that no
@@ -466,19 +474,19 @@ __device__ __forceinline__ void schedule_step()
 // buffer (k+1) % 3 was written in step k-1.  CI8 fragments are twice as
 // large: they are read at the start of their own step from buffer k % 3.
 //
-// V_CI4_DMA: kDmaDepth buffers, step k in buffer S = k % kDmaDepth.  Step k
+// V_CI4_DMA*: D buffers (the depth), step k in buffer S = k % D.  Step k
 // reads the fragments of step k+1, then refills buffer S (whose fragments,
-// step k's, were read in step k-1) with step k + kDmaDepth, runs the MFMAs
+// step k's, were read in step k-1) with step k + D, runs the MFMAs
 // of step k and, before the barrier, waits for its own copy of step k+2: the
-// copies of the kDmaDepth - 2 later steps may stay in flight.
+// copies of the D - 2 later steps may stay in flight.
 template <int FMT, int KIND, int S>
 __device__ __forceinline__ void pipeline_step(int k, Stager<FMT>& st, const Bufs& L, int si, int sj,
                                               int lane, const FragOfs& fo, Ops& ops, Acc& c)
 {
     constexpr int B = Geo<FMT>::kBufBytes;
     uint8_t* lds = L.p[0];
-    if constexpr (FMT == V_CI4_DMA) {
-        constexpr int D = kDmaDepth;
+    if constexpr (is_dma(FMT)) {
+        constexpr int D = dma_depth(FMT);
         st.load(L.p[S], k + D);
         Ops nx;
         if constexpr (KIND != KIND_NONE) {
@@ -551,7 +559,7 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
         }
     const int si = w.si, sj = w.sj;
     FragOfs fo;
-    if constexpr (FMT == V_CI4_DMA) {
+    if constexpr (is_dma(FMT)) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             fo.i[b] = tr_offset(si, b, lane);
@@ -564,10 +572,10 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
     // compiler can then count the loads in flight across the loop back-edge.
     constexpr int G = group_steps<FMT>();
     Ops ops;
-    if constexpr (FMT == V_CI4_DMA) {
+    if constexpr (is_dma(FMT)) {
         // Copies of steps 0..D-1 into buffers 0..D-1, operands of step 0;
         // the second barrier frees buffer 0 and publishes step 1.
-        constexpr int D = kDmaDepth;
+        constexpr int D = dma_depth(FMT);
 #pragma unroll
         for (int s = 0; s < D; ++s) st.load(L.p[s], s);
         dma_barrier<2 * (D - 1)>();
@@ -598,7 +606,7 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
         pipeline_group<FMT, KIND>(k0, st, L, si, sj, lane, fo, ops, c, std::make_integer_sequence<int, G>());
     // The copies issued by the last steps (zeros past the window) land
     // before the wave moves on.
-    if constexpr (FMT == V_CI4_DMA) wait_vm_lgkm<0>();
+    if constexpr (is_dma(FMT)) wait_vm_lgkm<0>();
     if (KIND == KIND_NONE) return;
 
     // Epilogue: 16x16 int32 result blocks hold column (lane % 16) and rows
@@ -636,23 +644,30 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
         }
 }
 
+// The LDS buffers of a variant (kernel-lifetime LDS variables).
 template <int FMT>
-__global__ void __launch_bounds__(kThreads, 1) xcorr_i8_kernel(LaunchArgs a)
+__device__ __forceinline__ Bufs lds_buffers()
 {
     constexpr int B = Geo<FMT>::kBufBytes;
     Bufs L;
-    if constexpr (FMT == V_CI4_DMA) {
+    if constexpr (is_dma(FMT)) {
         __shared__ __attribute__((aligned(16))) uint8_t b0[B], b1[B], b2[B], b3[B], b4[B], b5[B], b6[B], b7[B];
         uint8_t* const all[8] = {b0, b1, b2, b3, b4, b5, b6, b7};
 #pragma unroll
-        for (int i = 0; i < 8; ++i) L.p[i] = i < kDmaDepth ? all[i] : nullptr;
+        for (int i = 0; i < 8; ++i) L.p[i] = i < dma_depth(FMT) ? all[i] : nullptr;
     } else {
         __shared__ __attribute__((aligned(16))) uint8_t lds[3 * B];
 #pragma unroll
         for (int i = 0; i < 8; ++i) L.p[i] = i < 3 ? lds + i * B : nullptr;
     }
-    const int b = work_item_index(blockIdx.x, a.n_blocks, a.xcd_map);
-    if (b >= a.n_blocks) return;
+    return L;
+}
+
+// One work item (local index b of the launch arguments a) by the whole
+// workgroup.
+template <int FMT>
+__device__ __forceinline__ void process_item(const LaunchArgs& a, int b, const Bufs& L)
+{
     const WaveJobT<kWaves> w = wave_job<kWaves>(a, b);
     const int lane = threadIdx.x & 63;
     switch (w.kind) {
@@ -668,15 +683,88 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_kernel(LaunchArgs a)
     }
 }
 
-}  // namespace
+// One workgroup per work item of one plan's time chunk.
+template <int FMT>
+__global__ void __launch_bounds__(kThreads, 1) xcorr_i8_kernel(LaunchArgs a)
+{
+    const Bufs L = lds_buffers<FMT>();
+    const int b = work_item_index(blockIdx.x, a.n_blocks, a.xcd_map);
+    if (b >= a.n_blocks) return;
+    process_item<FMT>(a, b, L);
+}
 
-hipError_t launch_i8(const LaunchArgs& a, int fmt, hipStream_t s)
+// Persistent launch over the work items of several plans (subarrays of uneven
+// size and window length).  The items of all entries form one list; XCD x
+// owns the slice [slice[x], slice[x+1]) (contiguous, so a channel's workgroups
+// share that XCD's L2) and its workgroups take items from it in order through
+// the XCD's counter.  Every workgroup leaves once its slice is exhausted.
+template <int FMT>
+__global__ void __launch_bounds__(kThreads, 1) xcorr_i8_batch_kernel(BatchArgs ba)
+{
+    const Bufs L = lds_buffers<FMT>();
+    __shared__ int s_item;
+    const int q = ba.xcd_map ? (int)(blockIdx.x & 7) : 0;
+    const int lo = ba.xcd_map ? ba.slice[q] : ba.slice[0];
+    const int hi = ba.xcd_map ? ba.slice[q + 1] : ba.slice[8];
+    int* counter = ba.counters + q;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = lo + atomicAdd(counter, 1);
+        __syncthreads();
+        const int g = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (g >= hi) break;
+        int e = 0;
+        while (e + 1 < ba.n_entries && g >= ba.first[e + 1]) ++e;
+        process_item<FMT>(ba.e[e], g - ba.first[e], L);
+    }
+}
+
+template <int FMT>
+hipError_t launch_variant(const LaunchArgs& a, hipStream_t s)
 {
     const dim3 grid(launch_blocks(a.n_blocks, a.xcd_map)), block(kThreads);
-    if (fmt == 1)                  hipLaunchKernelGGL(xcorr_i8_kernel<V_CI8>, grid, block, 0, s, a);
-    else if (a.n_inputs % 16 == 0) hipLaunchKernelGGL(xcorr_i8_kernel<V_CI4_DMA>, grid, block, 0, s, a);
-    else                           hipLaunchKernelGGL(xcorr_i8_kernel<V_CI4>, grid, block, 0, s, a);
+    hipLaunchKernelGGL(xcorr_i8_kernel<FMT>, grid, block, 0, s, a);
     return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t launch_batch_variant(const BatchArgs& ba, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(xcorr_i8_batch_kernel<FMT>, dim3(grid), dim3(kThreads), 0, s, ba);
+    return hipGetLastError();
+}
+
+int variant_of(int fmt, int n_inputs, int tile)
+{
+    if (fmt == 1) return V_CI8;
+    if (tile == kTileRegs || n_inputs % 16 != 0) return V_CI4;
+    return tile == kTileDma4 ? V_CI4_DMA4 : V_CI4_DMA8;
+}
+
+}  // namespace
+
+hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, hipStream_t s)
+{
+    switch (variant_of(fmt, a.n_inputs, tile)) {
+    case V_CI8:      return launch_variant<V_CI8>(a, s);
+    case V_CI4:      return launch_variant<V_CI4>(a, s);
+    case V_CI4_DMA4: return launch_variant<V_CI4_DMA4>(a, s);
+    default:         return launch_variant<V_CI4_DMA8>(a, s);
+    }
+}
+
+hipError_t launch_i8_batch(const BatchArgs& ba, int fmt, int tile, int grid, hipStream_t s)
+{
+    // one variant for the whole launch: the DMA variants need every entry's
+    // n_inputs to be a multiple of 16
+    int n16 = 1;
+    for (int e = 0; e < ba.n_entries; ++e) n16 &= ba.e[e].n_inputs % 16 == 0;
+    switch (variant_of(fmt, n16 ? 16 : 4, tile)) {
+    case V_CI8:      return launch_batch_variant<V_CI8>(ba, grid, s);
+    case V_CI4:      return launch_batch_variant<V_CI4>(ba, grid, s);
+    case V_CI4_DMA4: return launch_batch_variant<V_CI4_DMA4>(ba, grid, s);
+    default:         return launch_batch_variant<V_CI4_DMA8>(ba, grid, s);
+    }
 }
 
 }  // namespace xcorr

@@ -128,13 +128,34 @@ inline int launch_blocks(int n_blocks, int xcd_map)
     return xcd_map ? ((n_blocks + 7) >> 3) << 3 : n_blocks;
 }
 
+// Arguments of one persistent batch launch: the launch arguments of up to
+// kMaxBatchEntries (plan, time chunk) entries, passed by value.
+constexpr int kMaxBatchEntries = 24;
+struct BatchArgs {
+    int32_t n_entries;
+    int32_t n_blocks;              // total work items over all entries
+    int32_t xcd_map;               // 1: per-XCD slices; 0: one list for all
+    int32_t pad;
+    int32_t first[kMaxBatchEntries + 1];   // first global item of each entry
+    int32_t slice[9];              // XCD x takes items [slice[x], slice[x+1])
+    int* counters;                 // 8 device counters, zero before the launch
+    LaunchArgs e[kMaxBatchEntries];
+};
+
+// Tile variants of the int8 kernel (xcorr_plan_desc.tile).
+constexpr int kTileDefault = 0;    // LDS-DMA, depth 8, where the shape allows
+constexpr int kTileDma8 = 1;       // LDS-DMA staging, 8 copies in flight
+constexpr int kTileDma4 = 2;       // LDS-DMA staging, 4 copies in flight
+constexpr int kTileRegs = 3;       // register staging (byte transposes + LDS writes)
+
 // Waves per workgroup of each kernel (the host plans work items to match).
 constexpr int kWavesI8 = 8;
 constexpr int kWavesF16 = 4;
 constexpr int kWavesF32 = 4;
 
 // Kernel launchers (one per arithmetic path); return the launch error.
-hipError_t launch_i8(const LaunchArgs& a, int fmt, hipStream_t s);
+hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, hipStream_t s);
+hipError_t launch_i8_batch(const BatchArgs& ba, int fmt, int tile, int grid, hipStream_t s);
 hipError_t launch_f16(const LaunchArgs& a, int fmt, hipStream_t s);
 hipError_t launch_f32(const LaunchArgs& a, int fmt, hipStream_t s);
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);

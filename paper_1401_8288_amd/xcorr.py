@@ -20,13 +20,17 @@ LIB_PATH = os.path.join(_HERE, "libxcorr.so")
 CI4, CI8 = 0, 1
 PATH_I8, PATH_F16, PATH_F32 = 0, 1, 2
 FLAG_NO_XCD_MAP = 0x2
+TILE_DEFAULT, TILE_DMA8, TILE_DMA4, TILE_REGS = 0, 1, 2, 3
 
 FORMATS = {"ci4": CI4, "ci8": CI8}
 PATHS = {"i8": PATH_I8, "f16": PATH_F16, "f32": PATH_F32}
 
 EXPORTS = ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dump",
            "xcorr_query", "xcorr_plan_bytes", "xcorr_destroy", "xcorr_strerror",
-           "xcorr_last_error", "xcorr_version")
+           "xcorr_last_error", "xcorr_version",
+           "xcorr_batch_create", "xcorr_batch_run", "xcorr_batch_get_config",
+           "xcorr_batch_set_config", "xcorr_batch_autotune", "xcorr_batch_capture",
+           "xcorr_graph_launch", "xcorr_graph_destroy", "xcorr_batch_destroy")
 
 
 class PlanDesc(ctypes.Structure):
@@ -46,6 +50,14 @@ class PlanInfo(ctypes.Structure):
                 ("input_bytes_per_sample", ctypes.c_size_t), ("fold_bound", ctypes.c_int64),
                 ("tile", ctypes.c_int32), ("work_items", ctypes.c_int32),
                 ("items_per_group", ctypes.c_int32), ("channels_per_group", ctypes.c_int32)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("grid", ctypes.c_int32), ("balance", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"tile": self.tile, "grid": self.grid, "balance": self.balance}
 
 
 class XcorrError(RuntimeError):
@@ -71,9 +83,19 @@ def _load():
     L.xcorr_strerror.restype = ctypes.c_char_p
     L.xcorr_last_error.restype = ctypes.c_char_p
     L.xcorr_version.restype = ctypes.c_int32
-    for name in ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dump",
-                 "xcorr_query", "xcorr_plan_bytes", "xcorr_destroy"):
-        getattr(L, name).restype = ctypes.c_int
+    P = ctypes.POINTER
+    L.xcorr_batch_create.argtypes = [P(vp), P(vp), i32, vp]
+    L.xcorr_batch_run.argtypes = [vp, P(vp), P(i64), P(vp), P(ctypes.c_int32), P(DumpInfo)]
+    L.xcorr_batch_get_config.argtypes = [vp, P(BatchConfig)]
+    L.xcorr_batch_set_config.argtypes = [vp, P(BatchConfig)]
+    L.xcorr_batch_autotune.argtypes = [vp, P(vp), P(i64), i32, P(BatchConfig), P(ctypes.c_float)]
+    L.xcorr_batch_capture.argtypes = [vp, P(vp), P(i64), P(vp), P(vp)]
+    L.xcorr_graph_launch.argtypes = [vp]
+    L.xcorr_graph_destroy.argtypes = [vp]
+    L.xcorr_batch_destroy.argtypes = [vp]
+    for name in EXPORTS:
+        if name not in ("xcorr_strerror", "xcorr_last_error", "xcorr_version"):
+            getattr(L, name).restype = ctypes.c_int
     return L
 
 
@@ -222,3 +244,120 @@ def correlate(x: torch.Tensor, fmt: str = "ci4", path: str = "i8") -> torch.Tens
     with Plan(n_in, n_ch, fmt, path) as p:
         out, _ = p.accumulate_dump(x)
     return out
+
+
+def _ptr_array(ptrs):
+    return (ctypes.c_void_p * len(ptrs))(*[ctypes.c_void_p(int(p)) for p in ptrs])
+
+
+class Batch:
+    """Several int8 plans (subarrays) run as one persistent launch per step.
+
+    The batch borrows the plans; they must stay open while it exists and must
+    not be used on their own while the batch runs.  Work is enqueued on
+    `stream` (default: torch's current stream).
+    """
+
+    def __init__(self, plans, stream: torch.cuda.Stream | None = None):
+        self.plans = list(plans)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        hs = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib.xcorr_batch_create(ctypes.byref(h), hs, len(self.plans),
+                                      ctypes.c_void_p(int(self.stream.cuda_stream))))
+        self._h = h
+
+    def _inputs(self, xs):
+        if len(xs) != len(self.plans):
+            raise ValueError("one input per plan (None for no samples)")
+        ptrs, nts = [], []
+        for p, x in zip(self.plans, xs):
+            if x is None:
+                ptrs.append(0)
+                nts.append(0)
+            else:
+                nts.append(p._check_input(x))
+                ptrs.append(x.data_ptr())
+        return _ptr_array(ptrs), (ctypes.c_int64 * len(nts))(*nts)
+
+    def _outputs(self, outs):
+        ptrs = []
+        for p, o in zip(self.plans, outs):
+            if o is None:
+                ptrs.append(0)
+            else:
+                p._check_output(o)
+                ptrs.append(o.data_ptr())
+        return _ptr_array(ptrs)
+
+    def run(self, xs, outs=None, reset=True):
+        """One step: xs[k] samples for plan k; dump plan k into outs[k] when given."""
+        d_in, nt = self._inputs(xs)
+        outs = outs if outs is not None else [None] * len(self.plans)
+        d_out = self._outputs(outs)
+        rs = (ctypes.c_int32 * len(self.plans))(*([int(bool(reset))] * len(self.plans)))
+        info = (DumpInfo * len(self.plans))()
+        _check(lib.xcorr_batch_run(self._h, d_in, nt, d_out, rs, info))
+        return [Dump(i.samples_accumulated, i.start_sample, i.n_dumps) if o is not None else None
+                for i, o in zip(info, outs)]
+
+    def config(self) -> dict:
+        c = BatchConfig()
+        _check(lib.xcorr_batch_get_config(self._h, ctypes.byref(c)))
+        return c.as_dict()
+
+    def set_config(self, tile=0, grid=256, balance=1):
+        c = BatchConfig(int(tile), int(grid), int(balance), 0)
+        _check(lib.xcorr_batch_set_config(self._h, ctypes.byref(c)))
+
+    def autotune(self, xs, reps: int = 3):
+        d_in, nt = self._inputs(xs)
+        c = BatchConfig()
+        ms = ctypes.c_float(0)
+        _check(lib.xcorr_batch_autotune(self._h, d_in, nt, int(reps), ctypes.byref(c), ctypes.byref(ms)))
+        return c.as_dict(), float(ms.value)
+
+    def capture(self, xs, outs) -> "Graph":
+        d_in, nt = self._inputs(xs)
+        d_out = self._outputs(outs)
+        g = ctypes.c_void_p()
+        _check(lib.xcorr_batch_capture(self._h, d_in, nt, d_out, ctypes.byref(g)))
+        return Graph(g, self)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib.xcorr_batch_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured integration step of a Batch (one full window per plan)."""
+
+    def __init__(self, h, batch):
+        self._h, self.batch = h, batch
+
+    def launch(self):
+        _check(lib.xcorr_graph_launch(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib.xcorr_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

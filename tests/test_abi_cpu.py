@@ -66,7 +66,10 @@ def _desc(**kw):
     (dict(n_inputs=6), -6),             # ci4 needs a multiple of 4 inputs
     (dict(n_inputs=5, fmt="ci8"), -6),  # ci8 needs a multiple of 2
     (dict(n_inputs=40000), -6),
-    (dict(flags=0x100), -1), (dict(tile=7), -1)])
+    (dict(flags=0x100), -1), (dict(tile=7), -1),
+    (dict(tile=1, n_inputs=36), -6),    # LDS-DMA tiles need n_inputs % 16 == 0
+    (dict(tile=2, fmt="ci8"), -6),      # ... and 4-bit samples
+    (dict(tile=3, path="f32"), -6)])    # tile variants exist for the int8 path only
 def test_bad_descriptors_rejected_before_any_device_call(kw, status):
     from paper_1401_8288_amd import xcorr
     h = ctypes.c_void_p()
@@ -108,3 +111,27 @@ def test_plan_bytes_is_the_accumulator(n_in, fmt, path):
     got = xcorr.plan_bytes(n_in, 4096, fmt, path)
     acc = nb * 4096 * 2 * (8 if path == "i8" else 4)
     assert acc <= got < acc + 65536
+
+
+def test_batch_and_graph_calls_on_invalid_handles():
+    from paper_1401_8288_amd import xcorr
+    L = xcorr.lib
+    bogus = ctypes.c_void_p(0x1234)
+    h = ctypes.c_void_p()
+    plans = (ctypes.c_void_p * 1)(0x1234)
+    assert L.xcorr_batch_create(None, plans, 1, None) == -1
+    assert L.xcorr_batch_create(ctypes.byref(h), None, 1, None) == -1
+    assert L.xcorr_batch_create(ctypes.byref(h), plans, 0, None) == -1
+    assert L.xcorr_batch_create(ctypes.byref(h), plans, 65, None) == -1
+    assert L.xcorr_batch_create(ctypes.byref(h), plans, 1, None) == -4   # not a plan
+    assert h.value is None
+    assert L.xcorr_batch_run(bogus, None, None, None, None, None) == -4
+    assert L.xcorr_batch_get_config(bogus, None) == -4
+    assert L.xcorr_batch_set_config(bogus, None) == -4
+    assert L.xcorr_batch_autotune(bogus, None, None, 1, None, None) == -4
+    assert L.xcorr_batch_capture(bogus, None, None, None, None) == -4
+    assert L.xcorr_graph_launch(bogus) == -4
+    assert L.xcorr_graph_destroy(bogus) == -4
+    assert L.xcorr_graph_destroy(None) == -4
+    assert L.xcorr_batch_destroy(bogus) == -4
+    assert L.xcorr_batch_destroy(None) == -4

@@ -155,6 +155,34 @@ def test_fp_paths_accumulate_across_calls(path):
     p.close()
 
 
+@pytest.mark.parametrize("shape", [(36, 3, 100), (128, 2, 129), (400, 1, 77)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("path", ["i8", "f16", "f32"])
+def test_ci8_with_minus_128(shape, path):
+    # components over the whole int8 range [-128, 127]
+    n_in, n_ch, n_t = shape
+    say("ci8 -128..127", shape, path)
+    x = synth.random_input(n_ch, n_t, n_in, "ci8", seed=n_in + 3 * n_t, lo=-128, hi=127, device=DEV)
+    assert int(x.min()) == -128
+    ref = oracle.correlate(x.cpu().numpy(), "ci8")
+    got, _ = run(x, "ci8", path)
+    if path == "i8":
+        np.testing.assert_array_equal(got, ref)
+    else:
+        assert n_t * 2 * 128 * 128 < 2 ** 24
+        np.testing.assert_array_equal(got, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("shape", [(64, 3, 1000), (512, 1, 333), (112, 5, 64)], ids=lambda s: "x".join(map(str, s)))
+def test_int8_tile_variants(tile, shape):
+    n_in, n_ch, n_t = shape
+    say("tile", tile, shape)
+    x = synth.random_input(n_ch, n_t, n_in, "ci4", seed=tile + n_in, device=DEV)
+    ref = oracle.correlate(x.cpu().numpy(), "ci4")
+    got, _ = run(x, "ci4", "i8", tile=tile)
+    np.testing.assert_array_equal(got, ref)
+
+
 @pytest.mark.parametrize("fmt,re,im,per_sample", [("ci4", -8, -8, 128), ("ci8", -128, -128, 32768),
                                                   ("ci8", 127, -128, 127 * 127 + 128 * 128)])
 def test_int32_fold_past_two_to_the_31(fmt, re, im, per_sample):
