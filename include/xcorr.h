@@ -188,6 +188,77 @@ xcorr_status xcorr_graph_destroy(xcorr_graph_t graph);
 /* Release the batch (waits for its stream); the plans stay valid. */
 xcorr_status xcorr_batch_destroy(xcorr_batch_t batch);
 
+/* ------------------------------------------------------------------------
+ * Server: a streaming loop over many integration streams (one stream = the
+ * X-stage of one (sub)array, windows arriving over time, Sec. 2.1 / Sec. 4).
+ *   - Streams are admitted by device memory: a stream needs the bytes of a
+ *     plan of its descriptor (xcorr_plan_bytes); it is admitted when a slot
+ *     and that much of the budget are free, else it waits (FIFO) and is
+ *     admitted when closed streams release theirs.
+ *   - A worker thread batches continuously: every launch takes the oldest
+ *     pending window of each admitted stream (windows that arrive while
+ *     others are on the GPU join the next launch) and runs them as one
+ *     persistent launch per format; up to max_inflight launches are queued on
+ *     the server's stream.
+ *   - Each window is accumulated and dumped with reset (one integration per
+ *     window); the caller keeps d_in and d_out valid until its ticket is done.
+ * Results do not depend on what else is in the batch (exact int8 path).
+ * ------------------------------------------------------------------------ */
+typedef struct xcorr_server_s* xcorr_server_t;
+
+typedef struct {
+    size_t device_budget;        /* bytes of plan memory the server may hold        */
+    int32_t max_streams;         /* admitted streams at once (1..64)                */
+    int32_t max_inflight;        /* launches queued on the stream at once (1..8)    */
+    void* stream;                /* hipStream_t for all work; NULL = null stream    */
+} xcorr_server_desc;
+
+typedef struct {
+    int64_t windows_done;        /* windows whose dump is complete                  */
+    int64_t launches;            /* batched launches issued                         */
+    double cmac;                 /* complex MACs of the completed windows           */
+    double elapsed_s;            /* first submit to last completion                 */
+    double latency_p50_ms;       /* submit -> dump complete, over completed windows */
+    double latency_p99_ms;
+    double latency_max_ms;
+    double mean_batch;           /* windows per launch                              */
+    int32_t streams_admitted;    /* currently admitted                              */
+    int32_t streams_waiting;     /* opened, waiting for memory or a slot            */
+    size_t device_bytes;         /* plan memory held now                            */
+} xcorr_server_stats;
+
+/* Create a server and start its worker thread (on the current device). */
+xcorr_status xcorr_server_create(xcorr_server_t* out, const xcorr_server_desc* desc);
+
+/* Open a stream with the plan descriptor desc (path must be
+ * XCORR_PATH_I8_MFMA; desc->stream is ignored).  *stream_id is set at once;
+ * admission happens now or later.  XCORR_ERR_NOMEM if the stream could never
+ * fit the budget. */
+xcorr_status xcorr_server_open(xcorr_server_t server, const xcorr_plan_desc* desc, int32_t* stream_id);
+
+/* Queue one window of n_time > 0 samples (device buffer d_in, layout of
+ * xcorr_accumulate) whose dump goes to d_out (layout of xcorr_dump).  The
+ * caller must have ordered the writes of d_in before this call (e.g. by
+ * synchronising the stream that produced it).  *ticket identifies it. */
+xcorr_status xcorr_server_submit(xcorr_server_t server, int32_t stream_id, const void* d_in, int64_t n_time,
+                                 void* d_out, int64_t* ticket);
+
+/* done = 1 once the window's dump is complete in d_out; then info (may be
+ * NULL) and latency_ms (submit -> completion, may be NULL) are filled.
+ * xcorr_server_wait blocks until done. */
+xcorr_status xcorr_server_poll(xcorr_server_t server, int64_t ticket, int32_t* done, xcorr_dump_info* info,
+                               double* latency_ms);
+xcorr_status xcorr_server_wait(xcorr_server_t server, int64_t ticket, xcorr_dump_info* info, double* latency_ms);
+
+/* Close a stream: no more submits; its plan memory is released once its
+ * queued windows are done, which may admit waiting streams. */
+xcorr_status xcorr_server_close(xcorr_server_t server, int32_t stream_id);
+
+xcorr_status xcorr_server_query(xcorr_server_t server, xcorr_server_stats* stats);
+
+/* Finish every queued window, stop the worker and release everything. */
+xcorr_status xcorr_server_destroy(xcorr_server_t server);
+
 const char* xcorr_strerror(xcorr_status status);
 const char* xcorr_last_error(void);
 

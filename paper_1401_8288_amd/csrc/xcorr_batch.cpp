@@ -211,6 +211,25 @@ xcorr_status check_config(xcorr_batch_t b, const xcorr_batch_config& c)
 
 }  // namespace
 
+namespace xcorr {
+
+xcorr_status run_fused_windows(hipStream_t stream, int* d_counters, const xcorr_batch_config& cfg,
+                               const std::vector<xcorr_plan_t>& plans, const std::vector<const void*>& d_in,
+                               const std::vector<int64_t>& n_time, const std::vector<void*>& d_out,
+                               std::vector<xcorr_dump_info>& info)
+{
+    xcorr_batch_s tmp;
+    tmp.plans = plans;
+    tmp.stream = stream;
+    tmp.format = plans.empty() ? 0 : plans[0]->d.format;
+    tmp.d_counters = d_counters;
+    std::vector<int32_t> resets(plans.size(), 1);
+    info.resize(plans.size());
+    return run_step(&tmp, d_in.data(), n_time.data(), d_out.data(), resets.data(), info.data(), cfg, false);
+}
+
+}  // namespace xcorr
+
 extern "C" {
 
 xcorr_status xcorr_batch_create(xcorr_batch_t* out, const xcorr_plan_t* plans, int32_t n_plans, void* stream)

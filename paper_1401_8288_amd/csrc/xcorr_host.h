@@ -42,5 +42,11 @@ LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_str
 void fill_info(const xcorr_plan_s* p, xcorr_dump_info* info);
 // Relative cost of a work item (MFMA blocks its waves own).
 int item_blocks(const WorkItem& it);
+// One fused window (accumulate + dump with reset) for each plan, all in one
+// persistent launch per time chunk.  The plans must share the format.
+xcorr_status run_fused_windows(hipStream_t stream, int* d_counters, const xcorr_batch_config& cfg,
+                               const std::vector<xcorr_plan_t>& plans, const std::vector<const void*>& d_in,
+                               const std::vector<int64_t>& n_time, const std::vector<void*>& d_out,
+                               std::vector<xcorr_dump_info>& info);
 
 }  // namespace xcorr

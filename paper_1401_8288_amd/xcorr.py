@@ -30,7 +30,9 @@ EXPORTS = ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dum
            "xcorr_last_error", "xcorr_version",
            "xcorr_batch_create", "xcorr_batch_run", "xcorr_batch_get_config",
            "xcorr_batch_set_config", "xcorr_batch_autotune", "xcorr_batch_capture",
-           "xcorr_graph_launch", "xcorr_graph_destroy", "xcorr_batch_destroy")
+           "xcorr_graph_launch", "xcorr_graph_destroy", "xcorr_batch_destroy",
+           "xcorr_server_create", "xcorr_server_open", "xcorr_server_submit", "xcorr_server_poll",
+           "xcorr_server_wait", "xcorr_server_close", "xcorr_server_query", "xcorr_server_destroy")
 
 
 class PlanDesc(ctypes.Structure):
@@ -58,6 +60,22 @@ class BatchConfig(ctypes.Structure):
 
     def as_dict(self):
         return {"tile": self.tile, "grid": self.grid, "balance": self.balance}
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("device_budget", ctypes.c_size_t), ("max_streams", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("windows_done", ctypes.c_int64), ("launches", ctypes.c_int64), ("cmac", ctypes.c_double),
+                ("elapsed_s", ctypes.c_double), ("latency_p50_ms", ctypes.c_double),
+                ("latency_p99_ms", ctypes.c_double), ("latency_max_ms", ctypes.c_double),
+                ("mean_batch", ctypes.c_double), ("streams_admitted", ctypes.c_int32),
+                ("streams_waiting", ctypes.c_int32), ("device_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class XcorrError(RuntimeError):
@@ -93,6 +111,14 @@ def _load():
     L.xcorr_graph_launch.argtypes = [vp]
     L.xcorr_graph_destroy.argtypes = [vp]
     L.xcorr_batch_destroy.argtypes = [vp]
+    L.xcorr_server_create.argtypes = [P(vp), P(ServerDesc)]
+    L.xcorr_server_open.argtypes = [vp, P(PlanDesc), P(ctypes.c_int32)]
+    L.xcorr_server_submit.argtypes = [vp, ctypes.c_int32, vp, i64, vp, P(i64)]
+    L.xcorr_server_poll.argtypes = [vp, i64, P(ctypes.c_int32), P(DumpInfo), P(ctypes.c_double)]
+    L.xcorr_server_wait.argtypes = [vp, i64, P(DumpInfo), P(ctypes.c_double)]
+    L.xcorr_server_close.argtypes = [vp, ctypes.c_int32]
+    L.xcorr_server_query.argtypes = [vp, P(ServerStats)]
+    L.xcorr_server_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("xcorr_strerror", "xcorr_last_error", "xcorr_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -355,6 +381,93 @@ class Graph:
         if getattr(self, "_h", None) is not None and self._h.value:
             _check(lib.xcorr_graph_destroy(self._h))
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Streaming server: streams admitted by device memory, windows batched
+    continuously by a native worker thread (see include/xcorr.h).
+
+    Inputs must be complete on the device when submitted (synchronise the
+    producing stream first); outputs are valid once their ticket is done.
+    """
+
+    def __init__(self, device_budget: int, max_streams: int = 16, max_inflight: int = 2,
+                 stream: torch.cuda.Stream | None = None):
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        d = ServerDesc(int(device_budget), int(max_streams), int(max_inflight),
+                       ctypes.c_void_p(int(self.stream.cuda_stream)))
+        h = ctypes.c_void_p()
+        _check(lib.xcorr_server_create(ctypes.byref(h), ctypes.byref(d)))
+        self._h = h
+        self._streams = {}
+
+    def open(self, n_inputs: int, n_channels: int, fmt: str = "ci4", tile: int = 0) -> int:
+        desc = make_desc(n_inputs, n_channels, fmt, "i8", tile=tile)
+        sid = ctypes.c_int32(0)
+        _check(lib.xcorr_server_open(self._h, ctypes.byref(desc), ctypes.byref(sid)))
+        self._streams[sid.value] = (n_inputs, n_channels, fmt)
+        return sid.value
+
+    def new_output(self, sid: int) -> torch.Tensor:
+        n, c, _ = self._streams[sid]
+        return torch.empty((c, n * (n + 1) // 2, 2), dtype=torch.int64, device=self.stream.device)
+
+    def submit(self, sid: int, x: torch.Tensor, out: torch.Tensor) -> int:
+        n, c, fmt = self._streams[sid]
+        if not x.is_contiguous() or x.shape[0] != c or x.shape[2] != n:
+            raise ValueError("input does not match stream %d" % sid)
+        if fmt == "ci4" and (x.dtype != torch.uint8 or x.dim() != 3):
+            raise ValueError("ci4 input must be uint8 [channel][time][input]")
+        if fmt == "ci8" and (x.dtype != torch.int8 or x.dim() != 4):
+            raise ValueError("ci8 input must be int8 [channel][time][input][2]")
+        if (out.dtype != torch.int64 or not out.is_contiguous()
+                or tuple(out.shape) != (c, n * (n + 1) // 2, 2)):
+            raise ValueError("output does not match stream %d" % sid)
+        t = ctypes.c_int64(0)
+        _check(lib.xcorr_server_submit(self._h, int(sid), ctypes.c_void_p(x.data_ptr()), int(x.shape[1]),
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int32(0)
+        info = DumpInfo()
+        lat = ctypes.c_double(0)
+        _check(lib.xcorr_server_poll(self._h, int(ticket), ctypes.byref(done), ctypes.byref(info),
+                                     ctypes.byref(lat)))
+        if not done.value:
+            return False, None, None
+        return True, Dump(info.samples_accumulated, info.start_sample, info.n_dumps), lat.value
+
+    def wait(self, ticket: int):
+        info = DumpInfo()
+        lat = ctypes.c_double(0)
+        _check(lib.xcorr_server_wait(self._h, int(ticket), ctypes.byref(info), ctypes.byref(lat)))
+        return Dump(info.samples_accumulated, info.start_sample, info.n_dumps), lat.value
+
+    def close_stream(self, sid: int):
+        _check(lib.xcorr_server_close(self._h, int(sid)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib.xcorr_server_query(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib.xcorr_server_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

@@ -135,3 +135,26 @@ def test_batch_and_graph_calls_on_invalid_handles():
     assert L.xcorr_graph_destroy(None) == -4
     assert L.xcorr_batch_destroy(bogus) == -4
     assert L.xcorr_batch_destroy(None) == -4
+
+
+def test_server_calls_on_invalid_handles_and_arguments():
+    from paper_1401_8288_amd import xcorr
+    L = xcorr.lib
+    bogus = ctypes.c_void_p(0x1234)
+    h = ctypes.c_void_p()
+    for budget, streams, inflight in ((0, 4, 2), (1 << 30, 0, 2), (1 << 30, 65, 2), (1 << 30, 4, 0), (1 << 30, 4, 9)):
+        d = xcorr.ServerDesc(budget, streams, inflight, None)
+        assert L.xcorr_server_create(ctypes.byref(h), ctypes.byref(d)) == -1
+        assert h.value is None
+    assert L.xcorr_server_create(None, None) == -1
+    sid = ctypes.c_int32(0)
+    t = ctypes.c_int64(0)
+    done = ctypes.c_int32(0)
+    assert L.xcorr_server_open(bogus, None, ctypes.byref(sid)) == -4
+    assert L.xcorr_server_submit(bogus, 1, None, 1, None, ctypes.byref(t)) == -4
+    assert L.xcorr_server_poll(bogus, 1, ctypes.byref(done), None, None) == -4
+    assert L.xcorr_server_wait(bogus, 1, None, None) == -4
+    assert L.xcorr_server_close(bogus, 1) == -4
+    assert L.xcorr_server_query(bogus, None) == -4
+    assert L.xcorr_server_destroy(bogus) == -4
+    assert L.xcorr_server_destroy(None) == -4
