@@ -122,6 +122,69 @@ def copy_calibration(torch, xcorr, x, w):
     p.close()
 
 
+def serving_leg(torch, xcorr, seconds, speedup, seed=7):
+    """Batched streaming: the five subarrays (32/96/192/400/704 inputs, 4-bit)
+    feed windows of 1024-4096 samples into the server as Poisson processes
+    whose mean gap is the window's duration (N_t x 40.96 us) divided by
+    `speedup`.  The deadline of a window is that same duration / speedup."""
+    import random
+    from paper_1401_8288_amd import synth
+    rng = random.Random(seed)
+    dev = torch.device("cuda:0")
+    lens = (1024, 2048, 3072, 4096)
+    pool, outs, busy = [], [], []
+    for k in range(len(synth.SUBARRAYS)):
+        pool.append({t: synth.generate(synth.subarray_workload(k, t), device=dev) for t in lens})
+    torch.cuda.synchronize()
+    srv = xcorr.Server(device_budget=64 << 30, max_streams=8, max_inflight=2)
+    sids = []
+    for k in range(len(synth.SUBARRAYS)):
+        w = synth.subarray_workload(k, 1024)
+        sids.append(srv.open(w.n_inputs, w.n_channels))
+        outs.append([srv.new_output(sids[-1]) for _ in range(4)])
+        busy.append([None] * 4)
+    # arrival schedule
+    events = []
+    for k in range(len(sids)):
+        t = 0.0
+        while True:
+            nt = rng.choice(lens)
+            dur = nt * synth.SPECTRUM_INTERVAL_S / speedup
+            t += rng.expovariate(1.0 / dur)
+            if t > seconds:
+                break
+            events.append((t, k, nt, dur))
+    events.sort()
+    tickets = []
+    t0 = time.perf_counter()
+    for (ta, k, nt, dur) in events:
+        delay = ta - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        slot = next((j for j in range(4) if busy[k][j] is None or srv.poll(busy[k][j])[0]), None)
+        if slot is None:
+            srv.wait(busy[k][0])
+            slot = 0
+        tk = srv.submit(sids[k], pool[k][nt], outs[k][slot])
+        busy[k][slot] = tk
+        tickets.append((tk, dur))
+    misses = 0
+    for tk, dur in tickets:
+        _, lat = srv.wait(tk)
+        misses += lat > dur * 1e3
+    st = srv.stats()
+    srv.close()
+    cmac_rt = sum(synth.subarray_workload(k, 1).cmac for k in range(len(sids))) / synth.SPECTRUM_INTERVAL_S
+    return {"workload": "5 subarrays of 16/48/96/200/352 dual-pol antennas, 512/1024/2048/256/128 channels, "
+                        "4+4-bit, Poisson windows of 1024-4096 samples",
+            "speedup_vs_real_time": speedup, "seconds": seconds, "windows": st["windows_done"],
+            "offered_tcmac_s": round(cmac_rt * speedup / 1e12, 3),
+            "achieved_tcmac_s": round(st["cmac"] / st["elapsed_s"] / 1e12, 3) if st["elapsed_s"] else None,
+            "latency_p50_ms": round(st["latency_p50_ms"], 3), "latency_p99_ms": round(st["latency_p99_ms"], 3),
+            "latency_max_ms": round(st["latency_max_ms"], 3), "deadline_misses": int(misses),
+            "launches": st["launches"], "mean_windows_per_launch": round(st["mean_batch"], 2)}
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The oracle on a bounded sample of the same workload (host cores)."""
     import oracle
@@ -151,6 +214,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-compare", action="store_true", help="skip the fp16 / fp32 kernels")
+    ap.add_argument("--serving-seconds", type=float, default=4.0,
+                    help="length of the batched-streaming leg (0 skips it)")
+    ap.add_argument("--serving-speedup", type=float, default=40.0,
+                    help="arrival rate of the streaming leg as a multiple of real time")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run the library copy kernel once (for counter calibration)")
     ap.add_argument("--pmc-summary", metavar="DIR",
@@ -223,6 +290,12 @@ def main():
         comp["speedup_int8_vs_fp32"] = round(comp["f32"]["ms_per_step"] / ms, 2)
         comp["speedup_int8_vs_fp16"] = round(comp["f16"]["ms_per_step"] / ms, 2)
         result["compare"] = comp
+        torch.cuda.empty_cache()
+
+    if args.serving_seconds > 0:
+        log("batched streaming leg: %.1f s at %.0fx real time" % (args.serving_seconds, args.serving_speedup))
+        result["serving"] = serving_leg(torch, xcorr, args.serving_seconds, args.serving_speedup)
+        log("serving:", result["serving"])
         torch.cuda.empty_cache()
 
     if not args.no_cpu:
