@@ -259,7 +259,7 @@ def main():
                    "format": w.fmt, "path": "int8 MFMA, int32 partials, int64 output",
                    "entry_point": "xcorr_accumulate_dump(reset=1)",
                    "work_items": info.work_items},
-        "roofline": {"bound": "mfma", "kernel": "xcorr_i8_kernel<V_CI4_DMA>",
+        "roofline": {"bound": "mfma", "kernel": "xcorr_i8_persist_kernel<V_CI4_DMA4>",
                      "achieved": round(tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
                      "frac": round(tops / PEAK_INT8_TOPS, 4), "traffic": None,
                      "algorithmic_ops_per_launch": 8 * cmac,

@@ -66,11 +66,13 @@ typedef enum {
 
 /* Plan flags. */
 #define XCORR_FLAG_NO_XCD_MAP 0x2u /* dispatch work items in plain order (for tests)  */
+#define XCORR_FLAG_NO_PERSIST 0x4u /* one workgroup per work item instead of the
+                                      persistent schedule (LDS-DMA tiles; for tests)  */
 
 /* Tile variants of the int8 path (xcorr_plan_desc.tile).  All give identical
  * (exact) results; they differ in how samples reach LDS.  The LDS-DMA variants
  * need XCORR_CI4 and n_inputs % 16 == 0. */
-#define XCORR_TILE_DEFAULT 0       /* LDS-DMA depth 8 where allowed, else registers */
+#define XCORR_TILE_DEFAULT 0       /* LDS-DMA depth 4 where allowed, else registers */
 #define XCORR_TILE_DMA8 1          /* buffer loads straight to LDS, 8 steps in flight */
 #define XCORR_TILE_DMA4 2          /* the same, 4 steps in flight                   */
 #define XCORR_TILE_REGS 3          /* loads to registers, byte transposes, LDS writes */

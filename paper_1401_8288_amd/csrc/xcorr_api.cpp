@@ -262,7 +262,7 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
     if (d->n_inputs % align)
         return fail(XCORR_ERR_UNSUPPORTED, "n_inputs must be a multiple of %d for this format",
                     align);
-    if (d->flags & ~XCORR_FLAG_NO_XCD_MAP)
+    if (d->flags & ~(XCORR_FLAG_NO_XCD_MAP | XCORR_FLAG_NO_PERSIST))
         return fail(XCORR_ERR_ARG, "unknown flags 0x%x", d->flags);
     if (d->tile < 0 || d->tile > kTileRegs) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
     if (d->tile != kTileDefault && d->path != XCORR_PATH_I8_MFMA)
@@ -284,7 +284,7 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
     const LaunchArgs a = chunk_args(p, in, chan_stride, t_len, src, dst);
     hipError_t e;
     switch (p->d.path) {
-    case XCORR_PATH_I8_MFMA: e = launch_i8(a, p->d.format, p->tile, p->stream); break;
+    case XCORR_PATH_I8_MFMA: e = launch_i8(a, p->d.format, p->tile, p->persist_grid, p->stream); break;
     case XCORR_PATH_F16_MFMA: e = launch_f16(a, p->d.format, p->stream); break;
     default: e = launch_f32(a, p->d.format, p->stream); break;
     }
@@ -367,6 +367,9 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
     p->n_b = (int64_t)d->n_inputs * (d->n_inputs + 1) / 2;
     p->out_bytes = (size_t)p->n_b * d->n_channels * 2 * elem_bytes(d->path);
     p->xcd_map = (d->flags & XCORR_FLAG_NO_XCD_MAP) ? 0 : 1;
+    // LDS-DMA chunks run as a persistent launch of one workgroup per CU
+    const int n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    p->persist_grid = (d->flags & XCORR_FLAG_NO_PERSIST) ? 0 : (n_cu + 7) / 8 * 8;
     // int8 path: int32 partial sums are exact for 65535 samples; fp paths
     // accumulate in fp32 without a count limit.
     p->fold_bound = d->path == XCORR_PATH_I8_MFMA ? 65535 : (int64_t)1 << 30;

@@ -260,7 +260,7 @@ xcorr_status xcorr_batch_create(xcorr_batch_t* out, const xcorr_plan_t* plans, i
     b->format = fmt;
     b->dma_ok = dma_ok;
     b->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    b->cfg.tile = dma_ok ? kTileDma8 : kTileRegs;
+    b->cfg.tile = dma_ok ? kTileDma4 : kTileRegs;
     b->cfg.grid = ((b->n_cu + 7) / 8) * 8;
     b->cfg.balance = 1;
     e = hipMalloc((void**)&b->d_counters, 8 * sizeof(int));
@@ -301,7 +301,7 @@ xcorr_status xcorr_batch_set_config(xcorr_batch_t b, const xcorr_batch_config* c
     if (!batch_live(b)) return fail(XCORR_ERR_STATE, "invalid batch handle");
     if (!c) return fail(XCORR_ERR_ARG, "null config");
     xcorr_batch_config v = *c;
-    if (v.tile == kTileDefault) v.tile = b->dma_ok ? kTileDma8 : kTileRegs;
+    if (v.tile == kTileDefault) v.tile = b->dma_ok ? kTileDma4 : kTileRegs;
     xcorr_status s = check_config(b, v);
     if (s != XCORR_OK) return s;
     b->cfg = v;
@@ -319,7 +319,7 @@ xcorr_status xcorr_batch_autotune(xcorr_batch_t b, const void* const* d_in, cons
         if (p->acc_valid || p->samples != 0)
             return fail(XCORR_ERR_STATE, "autotune needs every plan freshly reset");
     std::vector<int> tiles;
-    if (b->dma_ok) tiles = {kTileDma8, kTileDma4, kTileRegs};
+    if (b->dma_ok) tiles = {kTileDma4, kTileDma8, kTileRegs};
     else tiles = {kTileRegs};
     const int g1 = ((b->n_cu + 7) / 8) * 8;
     std::vector<xcorr_batch_config> cands;

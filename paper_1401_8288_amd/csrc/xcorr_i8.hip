@@ -51,9 +51,9 @@ constexpr int kPitch = 80;                 // LDS bytes per row (64 samples + 16
 // The DMA variant comes in two copy-pipeline depths (LDS buffers in flight),
 // 4 and 8; the plan's tile setting or the autotuner picks one.
 enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_DMA4 = 2, V_CI4_DMA8 = 3 };
-__device__ __forceinline__ constexpr bool is_ci4(int v) { return v != V_CI8; }
-__device__ __forceinline__ constexpr bool is_dma(int v) { return v == V_CI4_DMA4 || v == V_CI4_DMA8; }
-__device__ __forceinline__ constexpr int dma_depth(int v) { return v == V_CI4_DMA8 ? 8 : 4; }
+__host__ __device__ constexpr bool is_ci4(int v) { return v != V_CI8; }
+__host__ __device__ constexpr bool is_dma(int v) { return v == V_CI4_DMA4 || v == V_CI4_DMA8; }
+__host__ __device__ constexpr int dma_depth(int v) { return v == V_CI4_DMA8 ? 8 : 4; }
 
 // Register-staged variants: global loads run kPrefetch steps ahead of the
 // step they feed: a channel's first reader waits for HBM, and the other
@@ -399,8 +399,8 @@ struct Bufs {
 template <int N>
 __device__ __forceinline__ void wait_vm_lgkm()
 {
-    static_assert(N >= 0 && N < 16, "vmcnt field");
-    __builtin_amdgcn_s_waitcnt(N | (0x7 << 4));
+    static_assert(N >= 0 && N < 64, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | (0x7 << 4) | ((N >> 4) << 14));
 }
 
 // Workgroup barrier of the LDS-DMA pipeline.  A __syncthreads() fence would
@@ -531,20 +531,23 @@ __device__ __forceinline__ void pipeline_step(int k, Stager<FMT>& st, const Bufs
 }
 
 template <int FMT, int KIND, int... S>
-__device__ __forceinline__ void pipeline_group(int k0, Stager<FMT>& st, const Bufs& L, int si, int sj, int lane,
-                                               const FragOfs& fo, Ops& ops, Acc& c,
+__device__ __forceinline__ void pipeline_group(int k0, Stager<FMT>& st, const Bufs& L, int si, int sj,
+                                               int lane, const FragOfs& fo, Ops& ops, Acc& c,
                                                std::integer_sequence<int, S...>)
 {
     (pipeline_step<FMT, KIND, S>(k0 + S, st, L, si, sj, lane, fo, ops, c), ...);
 }
 
+// One work item.  st stages this item's samples.  For the LDS-DMA variants a
+// persistent workgroup passes the stager of its next item (has_next, nst): its
+// first steps are copied before this item's epilogue, and the next item then
+// starts with issue_prologue = false.
 template <int FMT, int KIND>
 __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane,
-                                         const Bufs& L)
+                                         const Bufs& L, Stager<FMT>& st, bool has_next, const Stager<FMT>& nst,
+                                         bool issue_prologue)
 {
     uint8_t* lds = L.p[0];
-    Stager<FMT> st;
-    st.init(a, w, lane);
     const int nk = (a.t_len + kStep - 1) / kStep;
 
     Acc c;
@@ -573,11 +576,14 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
     constexpr int G = group_steps<FMT>();
     Ops ops;
     if constexpr (is_dma(FMT)) {
-        // Copies of steps 0..D-1 into buffers 0..D-1, operands of step 0;
+        // Copies of steps 0..D-1 into buffers 0..D-1 (unless the previous
+        // item of a persistent workgroup issued them), operands of step 0;
         // the second barrier frees buffer 0 and publishes step 1.
         constexpr int D = dma_depth(FMT);
+        if (issue_prologue) {
 #pragma unroll
-        for (int s = 0; s < D; ++s) st.load(L.p[s], s);
+            for (int s = 0; s < D; ++s) st.load(L.p[s], s);
+        }
         dma_barrier<2 * (D - 1)>();
         if (KIND != KIND_NONE) {
             Raw<FMT> raw;
@@ -604,9 +610,17 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
     }
     for (int k0 = 0; k0 < nk; k0 += G)
         pipeline_group<FMT, KIND>(k0, st, L, si, sj, lane, fo, ops, c, std::make_integer_sequence<int, G>());
-    // The copies issued by the last steps (zeros past the window) land
-    // before the wave moves on.
-    if constexpr (is_dma(FMT)) wait_vm_lgkm<0>();
+    if constexpr (is_dma(FMT)) {
+        // The copies issued by the last steps (zeros past the window) land
+        // before the wave moves on.  Every wave passed the last barrier after
+        // its last fragment reads, so a persistent workgroup can now copy its
+        // next item's first steps, which then overlap this item's epilogue.
+        wait_vm_lgkm<0>();
+        if (has_next) {
+#pragma unroll
+            for (int s = 0; s < dma_depth(FMT); ++s) nst.load(L.p[s], s);
+        }
+    }
     if (KIND == KIND_NONE) return;
 
     // Epilogue: 16x16 int32 result blocks hold column (lane % 16) and rows
@@ -666,21 +680,38 @@ __device__ __forceinline__ Bufs lds_buffers()
 // One work item (local index b of the launch arguments a) by the whole
 // workgroup.
 template <int FMT>
+__device__ __forceinline__ void dispatch_kind(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane,
+                                              const Bufs& L, Stager<FMT>& st, bool has_next,
+                                              const Stager<FMT>& nst, bool issue_prologue)
+{
+    switch (w.kind) {
+    case KIND_HALF0:  run_tile<FMT, KIND_HALF0>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_HALF1:  run_tile<FMT, KIND_HALF1>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_DIAG_A: run_tile<FMT, KIND_DIAG_A>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_DIAG_B: run_tile<FMT, KIND_DIAG_B>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_QUART0: run_tile<FMT, KIND_QUART0>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_QUART1: run_tile<FMT, KIND_QUART1>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_QUART2: run_tile<FMT, KIND_QUART2>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_QUART3: run_tile<FMT, KIND_QUART3>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    default:          run_tile<FMT, KIND_NONE>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    }
+}
+
+template <int FMT>
 __device__ __forceinline__ void process_item(const LaunchArgs& a, int b, const Bufs& L)
 {
     const WaveJobT<kWaves> w = wave_job<kWaves>(a, b);
     const int lane = threadIdx.x & 63;
-    switch (w.kind) {
-    case KIND_HALF0:  run_tile<FMT, KIND_HALF0>(a, w, lane, L); break;
-    case KIND_HALF1:  run_tile<FMT, KIND_HALF1>(a, w, lane, L); break;
-    case KIND_DIAG_A: run_tile<FMT, KIND_DIAG_A>(a, w, lane, L); break;
-    case KIND_DIAG_B: run_tile<FMT, KIND_DIAG_B>(a, w, lane, L); break;
-    case KIND_QUART0: run_tile<FMT, KIND_QUART0>(a, w, lane, L); break;
-    case KIND_QUART1: run_tile<FMT, KIND_QUART1>(a, w, lane, L); break;
-    case KIND_QUART2: run_tile<FMT, KIND_QUART2>(a, w, lane, L); break;
-    case KIND_QUART3: run_tile<FMT, KIND_QUART3>(a, w, lane, L); break;
-    default:          run_tile<FMT, KIND_NONE>(a, w, lane, L); break;
-    }
+    Stager<FMT> st;
+    st.init(a, w, lane);
+    dispatch_kind<FMT>(a, w, lane, L, st, false, st, true);
+}
+
+__device__ __forceinline__ int entry_of(const BatchArgs& ba, int g)
+{
+    int e = 0;
+    while (e + 1 < ba.n_entries && g >= ba.first[e + 1]) ++e;
+    return e;
 }
 
 // One workgroup per work item of one plan's time chunk.
@@ -713,9 +744,51 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_batch_kernel(BatchArgs b
         const int g = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (g >= hi) break;
-        int e = 0;
-        while (e + 1 < ba.n_entries && g >= ba.first[e + 1]) ++e;
+        const int e = entry_of(ba, g);
         process_item<FMT>(ba.e[e], g - ba.first[e], L);
+    }
+}
+
+// Persistent LDS-DMA kernel: workgroup j of XCD x takes the items
+// slice[x] + j, slice[x] + j + P, ... (P workgroups per XCD; a static
+// schedule needs no atomics, so the next item is known in advance) and copies
+// the next item's first steps while it finishes the current one.
+template <int FMT>
+__global__ void __launch_bounds__(kThreads, 1) xcorr_i8_persist_kernel(BatchArgs ba)
+{
+    static_assert(is_dma(FMT), "persistent schedule of the LDS-DMA variants");
+    const Bufs L = lds_buffers<FMT>();
+    const int q = ba.xcd_map ? (int)(blockIdx.x & 7) : 0;
+    const int j = ba.xcd_map ? (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+    const int P = ba.xcd_map ? (int)(gridDim.x >> 3) : (int)gridDim.x;
+    const int lo = ba.xcd_map ? ba.slice[q] : ba.slice[0];
+    const int hi = ba.xcd_map ? ba.slice[q + 1] : ba.slice[8];
+    int g = lo + j;
+    if (g >= hi) return;
+    const int lane = threadIdx.x & 63;
+    int e = entry_of(ba, g);
+    WaveJobT<kWaves> w = wave_job<kWaves>(ba.e[e], g - ba.first[e]);
+    Stager<FMT> st;
+    st.init(ba.e[e], w, lane);
+    bool issue = true;
+    for (;;) {
+        const int gn = g + P;
+        const bool has_next = gn < hi;
+        int en = e;
+        WaveJobT<kWaves> wn = w;
+        Stager<FMT> nst = st;
+        if (has_next) {
+            en = entry_of(ba, gn);
+            wn = wave_job<kWaves>(ba.e[en], gn - ba.first[en]);
+            nst.init(ba.e[en], wn, lane);
+        }
+        dispatch_kind<FMT>(ba.e[e], w, lane, L, st, has_next, nst, issue);
+        if (!has_next) break;
+        g = gn;
+        e = en;
+        w = wn;
+        st = nst;
+        issue = false;
     }
 }
 
@@ -730,7 +803,30 @@ hipError_t launch_variant(const LaunchArgs& a, hipStream_t s)
 template <int FMT>
 hipError_t launch_batch_variant(const BatchArgs& ba, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(xcorr_i8_batch_kernel<FMT>, dim3(grid), dim3(kThreads), 0, s, ba);
+    if constexpr (is_dma(FMT))
+        hipLaunchKernelGGL(xcorr_i8_persist_kernel<FMT>, dim3(grid), dim3(kThreads), 0, s, ba);
+    else
+        hipLaunchKernelGGL(xcorr_i8_batch_kernel<FMT>, dim3(grid), dim3(kThreads), 0, s, ba);
+    return hipGetLastError();
+}
+
+// A single plan's chunk as a one-entry persistent launch (LDS-DMA variants).
+template <int FMT>
+hipError_t launch_persist_single(const LaunchArgs& a, int grid, hipStream_t s)
+{
+    BatchArgs ba;
+    __builtin_memset(&ba, 0, sizeof ba);
+    ba.n_entries = 1;
+    ba.n_blocks = a.n_blocks;
+    ba.xcd_map = a.xcd_map;
+    ba.first[0] = 0;
+    ba.first[1] = a.n_blocks;
+    ba.e[0] = a;
+    // equal slices rounded to whole channel groups
+    const int per = (a.n_blocks / a.n_items + 7) / 8 * a.n_items;
+    for (int x = 0; x <= 8; ++x) ba.slice[x] = x * per < a.n_blocks ? x * per : a.n_blocks;
+    const int g = a.xcd_map ? grid : (a.n_blocks < grid ? a.n_blocks : grid);
+    hipLaunchKernelGGL(xcorr_i8_persist_kernel<FMT>, dim3(g), dim3(kThreads), 0, s, ba);
     return hipGetLastError();
 }
 
@@ -738,18 +834,20 @@ int variant_of(int fmt, int n_inputs, int tile)
 {
     if (fmt == 1) return V_CI8;
     if (tile == kTileRegs || n_inputs % 16 != 0) return V_CI4;
-    return tile == kTileDma4 ? V_CI4_DMA4 : V_CI4_DMA8;
+    return tile == kTileDma8 ? V_CI4_DMA8 : V_CI4_DMA4;
 }
 
 }  // namespace
 
-hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, hipStream_t s)
+hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, hipStream_t s)
 {
     switch (variant_of(fmt, a.n_inputs, tile)) {
     case V_CI8:      return launch_variant<V_CI8>(a, s);
     case V_CI4:      return launch_variant<V_CI4>(a, s);
-    case V_CI4_DMA4: return launch_variant<V_CI4_DMA4>(a, s);
-    default:         return launch_variant<V_CI4_DMA8>(a, s);
+    case V_CI4_DMA4: return persist_grid ? launch_persist_single<V_CI4_DMA4>(a, persist_grid, s)
+                                         : launch_variant<V_CI4_DMA4>(a, s);
+    default:         return persist_grid ? launch_persist_single<V_CI4_DMA8>(a, persist_grid, s)
+                                         : launch_variant<V_CI4_DMA8>(a, s);
     }
 }
 

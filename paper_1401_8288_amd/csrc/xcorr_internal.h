@@ -143,7 +143,7 @@ struct BatchArgs {
 };
 
 // Tile variants of the int8 kernel (xcorr_plan_desc.tile).
-constexpr int kTileDefault = 0;    // LDS-DMA, depth 8, where the shape allows
+constexpr int kTileDefault = 0;    // LDS-DMA, depth 4, where the shape allows
 constexpr int kTileDma8 = 1;       // LDS-DMA staging, 8 copies in flight
 constexpr int kTileDma4 = 2;       // LDS-DMA staging, 4 copies in flight
 constexpr int kTileRegs = 3;       // register staging (byte transposes + LDS writes)
@@ -154,7 +154,9 @@ constexpr int kWavesF16 = 4;
 constexpr int kWavesF32 = 4;
 
 // Kernel launchers (one per arithmetic path); return the launch error.
-hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, hipStream_t s);
+// persist_grid > 0: LDS-DMA variants run as a persistent launch of that many
+// workgroups (a multiple of 8); 0: one workgroup per work item.
+hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, hipStream_t s);
 hipError_t launch_i8_batch(const BatchArgs& ba, int fmt, int tile, int grid, hipStream_t s);
 hipError_t launch_f16(const LaunchArgs& a, int fmt, hipStream_t s);
 hipError_t launch_f32(const LaunchArgs& a, int fmt, hipStream_t s);

@@ -169,7 +169,7 @@ xcorr_status launch_windows(xcorr_server_t s, const std::vector<xcorr_plan_t>& p
             nt.push_back(ws[k].n_time);
             out.push_back(ws[k].d_out);
         }
-        xcorr_batch_config cfg{g.first == 0 ? kTileDma8 : kTileRegs, ((s->n_cu + 7) / 8) * 8, 1, 0};
+        xcorr_batch_config cfg{g.first == 0 ? kTileDma4 : kTileRegs, ((s->n_cu + 7) / 8) * 8, 1, 0};
         std::vector<xcorr_dump_info> info;
         xcorr_status rc = run_fused_windows(s->stream, s->d_counters, cfg, gp, in, nt, out, info);
         if (rc != XCORR_OK) return rc;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libxcorr.so")
 CI4, CI8 = 0, 1
 PATH_I8, PATH_F16, PATH_F32 = 0, 1, 2
 FLAG_NO_XCD_MAP = 0x2
+FLAG_NO_PERSIST = 0x4
 TILE_DEFAULT, TILE_DMA8, TILE_DMA4, TILE_REGS = 0, 1, 2, 3
 
 FORMATS = {"ci4": CI4, "ci8": CI8}
