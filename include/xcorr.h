@@ -76,6 +76,7 @@ typedef enum {
 #define XCORR_TILE_DMA8 1          /* buffer loads straight to LDS, 8 steps in flight */
 #define XCORR_TILE_DMA4 2          /* the same, 4 steps in flight                   */
 #define XCORR_TILE_REGS 3          /* loads to registers, byte transposes, LDS writes */
+#define XCORR_TILE_W4 4            /* LDS-DMA, one wave per SIMD owning whole tiles (single plans) */
 
 typedef struct xcorr_plan_s* xcorr_plan_t;
 

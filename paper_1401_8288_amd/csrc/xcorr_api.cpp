@@ -239,10 +239,25 @@ void plan_items8(int W, std::vector<WorkItem>& items, int& ch_group)
     }
 }
 
-void plan_items(int path, int W, std::vector<WorkItem>& items, int& ch_group)
+void plan_items(int path, int tile, int W, std::vector<WorkItem>& items, int& ch_group)
 {
-    if (path == XCORR_PATH_I8_MFMA) plan_items8(W, items, ch_group);
+    if (path == XCORR_PATH_I8_MFMA && tile != kTileW4) plan_items8(W, items, ch_group);
     else plan_items4(W, items, ch_group);
+}
+
+// The four-wave int8 kernel as a one-entry persistent launch.
+hipError_t launch_w4(const LaunchArgs& a, int grid, hipStream_t s)
+{
+    BatchArgs ba;
+    std::memset(&ba, 0, sizeof ba);
+    ba.n_entries = 1;
+    ba.n_blocks = a.n_blocks;
+    ba.xcd_map = a.xcd_map;
+    ba.first[1] = a.n_blocks;
+    ba.e[0] = a;
+    const int per = (a.n_blocks / a.n_items + 7) / 8 * a.n_items;
+    for (int x = 0; x <= 8; ++x) ba.slice[x] = std::min(x * per, a.n_blocks);
+    return launch_i8w4(ba, a.xcd_map ? grid : std::min(grid, a.n_blocks), s);
 }
 
 size_t elem_bytes(int path) { return path == XCORR_PATH_I8_MFMA ? 8 : 4; }
@@ -264,10 +279,11 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
                     align);
     if (d->flags & ~(XCORR_FLAG_NO_XCD_MAP | XCORR_FLAG_NO_PERSIST))
         return fail(XCORR_ERR_ARG, "unknown flags 0x%x", d->flags);
-    if (d->tile < 0 || d->tile > kTileRegs) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
+    if (d->tile < 0 || d->tile > kTileW4) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
     if (d->tile != kTileDefault && d->path != XCORR_PATH_I8_MFMA)
         return fail(XCORR_ERR_UNSUPPORTED, "tile variants exist for the int8 path only");
-    if ((d->tile == kTileDma8 || d->tile == kTileDma4) && (d->format != XCORR_CI4 || d->n_inputs % 16))
+    if ((d->tile == kTileDma8 || d->tile == kTileDma4 || d->tile == kTileW4) &&
+        (d->format != XCORR_CI4 || d->n_inputs % 16))
         return fail(XCORR_ERR_UNSUPPORTED, "LDS-DMA tiles need 4-bit samples and n_inputs %% 16 == 0");
     return XCORR_OK;
 }
@@ -284,7 +300,10 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
     const LaunchArgs a = chunk_args(p, in, chan_stride, t_len, src, dst);
     hipError_t e;
     switch (p->d.path) {
-    case XCORR_PATH_I8_MFMA: e = launch_i8(a, p->d.format, p->tile, p->persist_grid, p->stream); break;
+    case XCORR_PATH_I8_MFMA:
+        e = p->tile == kTileW4 ? launch_w4(a, p->persist_grid ? p->persist_grid : 256, p->stream)
+                               : launch_i8(a, p->d.format, p->tile, p->persist_grid, p->stream);
+        break;
     case XCORR_PATH_F16_MFMA: e = launch_f16(a, p->d.format, p->stream); break;
     default: e = launch_f32(a, p->d.format, p->stream); break;
     }
@@ -339,7 +358,7 @@ xcorr_status xcorr_plan_bytes(const xcorr_plan_desc* d, size_t* bytes)
     if (!bytes) return fail(XCORR_ERR_ARG, "null output");
     std::vector<WorkItem> items;
     int cg;
-    plan_items(d->path, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, cg);
+    plan_items(d->path, d->tile, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, cg);
     *bytes = plan_device_bytes(d, items.size());
     return XCORR_OK;
 }
@@ -380,7 +399,7 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
 
     p->tile = d->tile;
     std::vector<WorkItem>& items = p->h_items;
-    plan_items(d->path, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, p->ch_group);
+    plan_items(d->path, d->tile, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, p->ch_group);
     p->n_items = (int)items.size();
     p->n_groups = (d->n_channels + p->ch_group - 1) / p->ch_group;
     const int64_t blocks = (int64_t)p->n_items * p->n_groups;
