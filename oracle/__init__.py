@@ -17,6 +17,12 @@ Contents
   hermitian_form -- w^H V w evaluated from a lower-triangle result.
   brute_force    -- pure-Python integer loops for tiny inputs.
   matmul_form    -- the same sums as exact int64 numpy matrix products.
+  corner_turn    -- F-engine packet order -> X-stage input order, with the
+                    4 -> 8 bit promotion and zeros for lost packets (Sec. 2.4:
+                    packets placed by sequence number and F-engine; the
+                    unpacker pads 4 to 8 bits and reorders the channels of
+                    the F-engines next to each other; packet-format figure:
+                    the spectra of a packet follow one another).
 
 Formats: "ci4" = one byte per sample, high nibble real, low nibble imaginary,
 two's complement (Sec. 2.3: 4 bits real and 4 bits imaginary); "ci8" = two
@@ -233,3 +239,27 @@ def matmul_form(x: np.ndarray, fmt: str) -> np.ndarray:
         out[c, :, 0] = vr[i, j]
         out[c, :, 1] = vi[i, j]
     return out
+
+
+def corner_turn(packets: np.ndarray, n_fengines: int, inputs_per_feng: int, n_channels: int,
+                spectra_per_packet: int, valid: np.ndarray | None = None, out_fmt: str = "ci4") -> np.ndarray:
+    """X-stage input from captured F-engine packets.
+
+    packets: uint8 [n_blocks][n_fengines][spectra_per_packet][n_channels][inputs_per_feng],
+    one 4+4-bit sample per byte; block b, spectrum s is time b * S + s and
+    F-engine f, input j is X-stage input f * J + j.  valid[b][f] == 0 marks a
+    lost packet, whose samples are zero.  Returns ci4 bytes
+    [n_channels][time][inputs] or, for out_fmt "ci8", int8 [..][inputs][2]
+    (real, imaginary) with each nibble sign-extended.
+    """
+    F, J, C, S = n_fengines, inputs_per_feng, n_channels, spectra_per_packet
+    p = np.asarray(packets, dtype=np.uint8).reshape(-1, F, S, C, J)
+    B = p.shape[0]
+    if valid is not None:
+        p = p * (np.asarray(valid).reshape(B, F)[:, :, None, None, None] != 0).astype(np.uint8)
+    x = np.ascontiguousarray(p.transpose(3, 0, 2, 1, 4)).reshape(C, B * S, F * J)
+    if out_fmt == "ci4":
+        return x
+    re = x.view(np.int8) >> 4
+    im = (x << 4).view(np.int8) >> 4
+    return np.stack([re, im], axis=-1).astype(np.int8)
