@@ -185,6 +185,39 @@ def serving_leg(torch, xcorr, seconds, speedup, seed=7):
             "launches": st["launches"], "mean_windows_per_launch": round(st["mean_batch"], 2)}
 
 
+def corner_turn_leg(torch, xcorr, w, reps=5, n_fengines=16, spectra_per_packet=8):
+    """The corner turn in front of the X-stage at the workload's size: packets
+    of `spectra_per_packet` spectra from `n_fengines` F-engines (16 x 32 inputs
+    for 512), reordered to [channel][time][input]; HBM-bound (one read, one
+    write of every byte)."""
+    J = w.n_inputs // n_fengines
+    S = spectra_per_packet
+    B = w.n_time // S
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(11)
+    packets = torch.randint(0, 256, (B * n_fengines * S * w.n_channels * J,), dtype=torch.uint8,
+                            device=dev, generator=g)
+    out = torch.empty((w.n_channels, B * S, w.n_inputs), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    xcorr.corner_turn(packets, n_fengines, J, w.n_channels, S, out=out, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        xcorr.corner_turn(packets, n_fengines, J, w.n_channels, S, out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * packets.numel()
+    del packets, out
+    torch.cuda.empty_cache()
+    return {"layout": "%d F-engines x %d inputs, %d spectra per packet, %d channels, %d packets per F-engine"
+                      % (n_fengines, J, S, w.n_channels, B),
+            "ms": round(ms, 4), "bytes_moved": nbytes, "gbs": round(nbytes / ms / 1e6, 1),
+            "hbm_frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 4)}
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The oracle on a bounded sample of the same workload (host cores)."""
     import oracle
@@ -214,6 +247,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-compare", action="store_true", help="skip the fp16 / fp32 kernels")
+    ap.add_argument("--no-corner-turn", action="store_true", help="skip the corner-turn leg")
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="length of the batched-streaming leg (0 skips it)")
     ap.add_argument("--serving-speedup", type=float, default=40.0,
@@ -291,6 +325,11 @@ def main():
         comp["speedup_int8_vs_fp16"] = round(comp["f16"]["ms_per_step"] / ms, 2)
         result["compare"] = comp
         torch.cuda.empty_cache()
+
+    if not args.no_corner_turn:
+        log("corner turn at the same size")
+        result["corner_turn"] = corner_turn_leg(torch, xcorr, w)
+        log("corner turn:", result["corner_turn"])
 
     if args.serving_seconds > 0:
         log("batched streaming leg: %.1f s at %.0fx real time" % (args.serving_seconds, args.serving_speedup))

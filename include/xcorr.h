@@ -138,6 +138,36 @@ xcorr_status xcorr_plan_bytes(const xcorr_plan_desc* desc, size_t* bytes);
 xcorr_status xcorr_destroy(xcorr_plan_t plan);
 
 /* ------------------------------------------------------------------------
+ * Corner turn (Sec. 2.4): the X-stage input of a GPU assembled from captured
+ * F-engine packets.  Capture places each packet by its sequence number
+ * (block) and F-engine; a packet carries, for its spectra_per_packet
+ * consecutive spectra one after another, every channel's inputs of that
+ * F-engine (packet-format figure).  Completing the corner turn puts the
+ * inputs of all F-engines of one channel and time next to each other; the
+ * paper's unpacker also pads 4-bit samples to 8 bits (out_format XCORR_CI8).
+ *
+ *   d_packets  device, uint8 [n_blocks][n_fengines][S][n_channels][J],
+ *              one 4+4-bit sample per byte, 16-byte aligned
+ *   d_valid    device, uint8 [n_blocks][n_fengines], 0 = packet lost (its
+ *              samples become zeros); NULL = all received
+ *   d_out      device, [n_channels][n_blocks*S][n_fengines*J] bytes
+ *              (XCORR_CI4) or [...][2] int8 (XCORR_CI8), 16-byte aligned:
+ *              time = block * S + s, input = f * J + j
+ * J = inputs_per_feng must be a multiple of 4; n_fengines * J <= 32768.
+ * Enqueued on `stream`; nothing is allocated.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_blocks;            /* packets per F-engine in the buffer (sequence numbers) */
+    int32_t n_fengines;          /* F-engines (FPGA nodes)                              */
+    int32_t inputs_per_feng;     /* J, inputs per F-engine                              */
+    int32_t n_channels;          /* channels of this GPU                                */
+    int32_t spectra_per_packet;  /* S, consecutive spectra per packet                   */
+} xcorr_packet_layout;
+
+xcorr_status xcorr_corner_turn(const void* d_packets, const uint8_t* d_valid, const xcorr_packet_layout* layout,
+                               int32_t out_format, void* d_out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batches: several plans (subarrays of uneven input and channel counts, the
  * X-stage of several arrays sharing one GPU, Sec. 3) run as ONE persistent
  * launch per time chunk.  Every plan of a batch must use XCORR_PATH_I8_MFMA

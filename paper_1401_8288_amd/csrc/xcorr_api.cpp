@@ -1,6 +1,7 @@
 // Host side of libxcorr: argument checking, plan state, work decomposition
 // and the launch sequence of accumulate / dump.  See include/xcorr.h.
 #include "xcorr_host.h"
+#include "xcorr_ct.h"
 
 #include <algorithm>
 #include <cstdarg>
@@ -510,6 +511,36 @@ xcorr_status xcorr_query(xcorr_plan_t p, xcorr_plan_info* info)
     info->work_items = p->n_items * p->n_groups;
     info->items_per_group = p->n_items;
     info->channels_per_group = p->ch_group;
+    return XCORR_OK;
+}
+
+xcorr_status xcorr_corner_turn(const void* d_packets, const uint8_t* d_valid, const xcorr_packet_layout* L,
+                               int32_t out_format, void* d_out, void* stream)
+{
+    if (!L) return fail(XCORR_ERR_ARG, "null layout");
+    if (L->n_blocks < 1 || L->n_fengines < 1 || L->inputs_per_feng < 1 || L->n_channels < 1 ||
+        L->spectra_per_packet < 1)
+        return fail(XCORR_ERR_ARG, "every layout size must be >= 1");
+    if (L->inputs_per_feng % 4) return fail(XCORR_ERR_UNSUPPORTED, "inputs_per_feng must be a multiple of 4");
+    const int64_t n_in = (int64_t)L->n_fengines * L->inputs_per_feng;
+    if (n_in > 32768) return fail(XCORR_ERR_UNSUPPORTED, "n_fengines * inputs_per_feng above 32768");
+    if (out_format != XCORR_CI4 && out_format != XCORR_CI8) return fail(XCORR_ERR_ARG, "unknown out_format %d", out_format);
+    xcorr_status s = check_ptr(d_packets, "d_packets");
+    if (s == XCORR_OK) s = check_ptr(d_out, "d_out");
+    if (s != XCORR_OK) return s;
+    CornerTurnArgs a{};
+    a.in = (const uint8_t*)d_packets;
+    a.valid = d_valid;
+    a.out = d_out;
+    a.n_blocks = L->n_blocks;
+    a.n_fengines = L->n_fengines;
+    a.inputs_per_feng = L->inputs_per_feng;
+    a.n_channels = L->n_channels;
+    a.spectra = L->spectra_per_packet;
+    a.n_inputs = (int32_t)n_in;
+    a.n_time = (int64_t)L->n_blocks * L->spectra_per_packet;
+    hipError_t e = launch_corner_turn(a, out_format, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "corner turn launch");
     return XCORR_OK;
 }
 

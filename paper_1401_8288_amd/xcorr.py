@@ -33,7 +33,8 @@ EXPORTS = ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dum
            "xcorr_batch_set_config", "xcorr_batch_autotune", "xcorr_batch_capture",
            "xcorr_graph_launch", "xcorr_graph_destroy", "xcorr_batch_destroy",
            "xcorr_server_create", "xcorr_server_open", "xcorr_server_submit", "xcorr_server_poll",
-           "xcorr_server_wait", "xcorr_server_close", "xcorr_server_query", "xcorr_server_destroy")
+           "xcorr_server_wait", "xcorr_server_close", "xcorr_server_query", "xcorr_server_destroy",
+           "xcorr_corner_turn")
 
 
 class PlanDesc(ctypes.Structure):
@@ -79,6 +80,12 @@ class ServerStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class PacketLayout(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int32), ("n_fengines", ctypes.c_int32),
+                ("inputs_per_feng", ctypes.c_int32), ("n_channels", ctypes.c_int32),
+                ("spectra_per_packet", ctypes.c_int32)]
+
+
 class XcorrError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("xcorr status %d: %s" % (status, message))
@@ -120,6 +127,7 @@ def _load():
     L.xcorr_server_close.argtypes = [vp, ctypes.c_int32]
     L.xcorr_server_query.argtypes = [vp, P(ServerStats)]
     L.xcorr_server_destroy.argtypes = [vp]
+    L.xcorr_corner_turn.argtypes = [vp, vp, P(PacketLayout), i32, vp, vp]
     for name in EXPORTS:
         if name not in ("xcorr_strerror", "xcorr_last_error", "xcorr_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -475,3 +483,34 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def corner_turn(packets: torch.Tensor, n_fengines: int, inputs_per_feng: int, n_channels: int,
+                spectra_per_packet: int, valid: torch.Tensor | None = None, out_fmt: str = "ci4",
+                out: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """X-stage input from captured F-engine packets (see xcorr_corner_turn)."""
+    if packets.dtype != torch.uint8 or not packets.is_contiguous() or not packets.is_cuda:
+        raise ValueError("packets must be a contiguous uint8 device tensor")
+    per_block = n_fengines * spectra_per_packet * n_channels * inputs_per_feng
+    if packets.numel() % per_block:
+        raise ValueError("packet buffer size is not a whole number of blocks")
+    n_blocks = packets.numel() // per_block
+    n_in = n_fengines * inputs_per_feng
+    shape = (n_channels, n_blocks * spectra_per_packet, n_in)
+    if out_fmt == "ci8":
+        shape = shape + (2,)
+    dt = torch.uint8 if out_fmt == "ci4" else torch.int8
+    if out is None:
+        out = torch.empty(shape, dtype=dt, device=packets.device)
+    elif tuple(out.shape) != shape or out.dtype != dt or not out.is_contiguous():
+        raise ValueError("output must be a contiguous %s tensor %s" % (dt, shape))
+    if valid is not None and (valid.dtype != torch.uint8 or valid.numel() != n_blocks * n_fengines
+                              or not valid.is_contiguous() or valid.device != packets.device):
+        raise ValueError("valid must be a contiguous uint8 device tensor [n_blocks][n_fengines]")
+    lay = PacketLayout(n_blocks, n_fengines, inputs_per_feng, n_channels, spectra_per_packet)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.xcorr_corner_turn(ctypes.c_void_p(packets.data_ptr()),
+                                 ctypes.c_void_p(valid.data_ptr() if valid is not None else 0),
+                                 ctypes.byref(lay), FORMATS[out_fmt], ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(int(s.cuda_stream))))
+    return out
