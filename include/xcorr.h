@@ -127,6 +127,28 @@ xcorr_status xcorr_dump(xcorr_plan_t plan, void* d_out, int reset, xcorr_dump_in
 xcorr_status xcorr_accumulate_dump(xcorr_plan_t plan, const void* d_in, int64_t n_time,
                                    void* d_out, int reset, xcorr_dump_info* info);
 
+/* Baseline-dependent integration (Sec. 5): dump only the baselines of the
+ * selected 64 x 64 input-block tiles and, if reset != 0, restart their
+ * integration, while the others keep integrating.  tile_select is a HOST
+ * array of nr (nr + 1) / 2 bytes, nr = ceil(n_inputs / 64), in lower-triangle
+ * tile order: tile (ti, tj), ti >= tj, at ti (ti + 1) / 2 + tj; nonzero =
+ * selected.  Entries of d_out outside the selected tiles are left unchanged;
+ * info->samples_accumulated counts samples since the plan's last full reset
+ * (the per-tile count is the caller's cadence). */
+xcorr_status xcorr_dump_tiles(xcorr_plan_t plan, void* d_out, const uint8_t* tile_select, int reset,
+                              xcorr_dump_info* info);
+
+/* Pulsar gating (Sec. 5): sample t of the window d_in (n_time samples,
+ * layout of xcorr_accumulate) is integrated into plans[gate[t]]; gate is a
+ * HOST array of n_time bytes, each < n_gates or 0xFF (sample discarded).
+ * The plans (1..64, distinct) must share n_inputs, n_channels, format and
+ * stream, and use the int8 path.  The runs of equal gate go out as batched
+ * persistent launches, a round at a time (each round touches every gate's
+ * accumulator at most once); runs much shorter than 64 samples waste MFMA
+ * work on padding.  Dump each gate's plan with xcorr_dump. */
+xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, const void* d_in, int64_t n_time,
+                                    const uint8_t* gate);
+
 /* Sizes and the work decomposition chosen for the plan. */
 xcorr_status xcorr_query(xcorr_plan_t plan, xcorr_plan_info* info);
 

@@ -2,6 +2,7 @@
 // and the launch sequence of accumulate / dump.  See include/xcorr.h.
 #include "xcorr_host.h"
 #include "xcorr_ct.h"
+#include "xcorr_tiles.h"
 
 #include <algorithm>
 #include <cstdarg>
@@ -292,7 +293,7 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
 size_t plan_device_bytes(const xcorr_plan_desc* d, size_t n_items)
 {
     const int64_t n_b = (int64_t)d->n_inputs * (d->n_inputs + 1) / 2;
-    return (size_t)n_b * d->n_channels * 2 * elem_bytes(d->path) + n_items * sizeof(WorkItem) + 256;
+    return (size_t)n_b * d->n_channels * 2 * elem_bytes(d->path) + n_items * sizeof(WorkItem) + 256 + 32;
 }
 
 xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
@@ -411,9 +412,11 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
 
     e = hipMalloc(&p->acc, p->out_bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, items.size() * sizeof(WorkItem));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_counters, 8 * sizeof(int));
     if (e != hipSuccess) {
         release(p->acc);
         release(p->d_items);
+        release(p->d_counters);
         delete p;
         (void)hipGetLastError();
         return fail(e == hipErrorOutOfMemory ? XCORR_ERR_NOMEM : XCORR_ERR_DEVICE,
@@ -423,6 +426,7 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
     if (e != hipSuccess) {
         release(p->acc);
         release(p->d_items);
+        release(p->d_counters);
         delete p;
         return hip_fail(e, "work item upload");
     }
@@ -514,6 +518,32 @@ xcorr_status xcorr_query(xcorr_plan_t p, xcorr_plan_info* info)
     return XCORR_OK;
 }
 
+xcorr_status xcorr_dump_tiles(xcorr_plan_t p, void* d_out, const uint8_t* tile_select, int reset,
+                              xcorr_dump_info* info)
+{
+    if (!live(p)) return fail(XCORR_ERR_STATE, "invalid plan handle");
+    if (!tile_select) return fail(XCORR_ERR_ARG, "null tile selection");
+    xcorr_status s = check_ptr(d_out, "d_out");
+    if (s != XCORR_OK) return s;
+    const int nr = (p->d.n_inputs + kRowBlock - 1) / kRowBlock;
+    const size_t nsel = (size_t)nr * (nr + 1) / 2;
+    hipError_t e = hipSuccess;
+    if (!p->d_tile_sel) e = hipMalloc((void**)&p->d_tile_sel, nsel);
+    if (e != hipSuccess) {
+        p->d_tile_sel = nullptr;
+        (void)hipGetLastError();
+        return fail(XCORR_ERR_NOMEM, "tile selection: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpyAsync(p->d_tile_sel, tile_select, nsel, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess)
+        e = launch_dump_tiles(d_out, p->acc, p->acc_valid ? 1 : 0, p->d_tile_sel, p->d.n_inputs, p->d.n_channels,
+                              (int)(2 * elem_bytes(p->d.path)), reset ? 1 : 0, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "tile dump");
+    p->n_dumps += 1;
+    fill_info(p, info);
+    return XCORR_OK;
+}
+
 xcorr_status xcorr_corner_turn(const void* d_packets, const uint8_t* d_valid, const xcorr_packet_layout* L,
                                int32_t out_format, void* d_out, void* stream)
 {
@@ -553,6 +583,8 @@ xcorr_status xcorr_destroy(xcorr_plan_t p)
     hipError_t e = hipStreamSynchronize(p->stream);
     release(p->acc);
     release(p->d_items);
+    release(p->d_counters);
+    release(p->d_tile_sel);
     delete p;
     if (e != hipSuccess) return hip_fail(e, "destroy: stream synchronize");
     return XCORR_OK;

@@ -444,6 +444,85 @@ xcorr_status xcorr_graph_destroy(xcorr_graph_t g)
     return XCORR_OK;
 }
 
+xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, const void* d_in, int64_t n_time,
+                                    const uint8_t* gate)
+{
+    if (!plans || n_gates < 1 || n_gates > 64) return fail(XCORR_ERR_ARG, "n_gates must be 1..64");
+    if (n_time < 0) return fail(XCORR_ERR_ARG, "negative n_time");
+    for (int g = 0; g < n_gates; ++g) {
+        if (!plan_live(plans[g])) return fail(XCORR_ERR_STATE, "gate plan %d is not valid", g);
+        const xcorr_plan_s* p = plans[g];
+        const xcorr_plan_s* p0 = plans[0];
+        if (p->d.path != XCORR_PATH_I8_MFMA || p->tile == kTileW4)
+            return fail(XCORR_ERR_UNSUPPORTED, "gated accumulation runs the batched int8 path");
+        if (p->d.n_inputs != p0->d.n_inputs || p->d.n_channels != p0->d.n_channels || p->d.format != p0->d.format ||
+            p->stream != p0->stream)
+            return fail(XCORR_ERR_ARG, "gate plans must share inputs, channels, format and stream");
+        for (int h = 0; h < g; ++h)
+            if (plans[h] == plans[g]) return fail(XCORR_ERR_ARG, "gate plan %d appears twice", g);
+    }
+    if (n_time == 0) return XCORR_OK;
+    if (!gate) return fail(XCORR_ERR_ARG, "null gate array");
+    xcorr_status st = check_ptr(d_in, "d_in");
+    if (st != XCORR_OK) return st;
+    for (int64_t t = 0; t < n_time; ++t)
+        if (gate[t] != 0xFF && gate[t] >= n_gates) return fail(XCORR_ERR_ARG, "gate[%lld] out of range", (long long)t);
+
+    // runs of equal gate, split at the fold bound; the k-th run of a gate
+    // goes into round k so that a round touches each accumulator once
+    struct Run { int g; int64_t t0, len; };
+    std::vector<std::vector<Run>> rounds;
+    std::vector<int> count(n_gates, 0);
+    for (int64_t t = 0; t < n_time;) {
+        int64_t e = t + 1;
+        while (e < n_time && gate[e] == gate[t]) ++e;
+        if (gate[t] != 0xFF) {
+            const int g = gate[t];
+            for (int64_t c = t; c < e; c += plans[g]->fold_bound) {
+                const int k = count[g]++;
+                if ((int)rounds.size() <= k) rounds.resize(k + 1);
+                rounds[k].push_back(Run{g, c, std::min<int64_t>(plans[g]->fold_bound, e - c)});
+            }
+        }
+        t = e;
+    }
+    xcorr_plan_s* p0 = plans[0];
+    xcorr_batch_s tmp;
+    tmp.plans.assign(plans, plans + n_gates);
+    tmp.stream = p0->stream;
+    tmp.format = p0->d.format;
+    tmp.d_counters = p0->d_counters;
+    const bool dma = p0->d.format == XCORR_CI4 && p0->d.n_inputs % 16 == 0 && p0->tile != kTileRegs;
+    const xcorr_batch_config cfg{dma ? (p0->tile == kTileDma8 ? kTileDma8 : kTileDma4) : kTileRegs,
+                                 p0->persist_grid ? p0->persist_grid : 256, 1, 0};
+    const int64_t row = row_bytes_of(p0);
+    std::vector<char> valid(n_gates);
+    for (int g = 0; g < n_gates; ++g) valid[g] = plans[g]->acc_valid;
+    std::vector<int64_t> added(n_gates, 0);
+    for (const std::vector<Run>& round : rounds) {
+        std::vector<Entry> es;
+        for (const Run& r : round) {
+            xcorr_plan_s* p = plans[r.g];
+            Entry en;
+            en.a = chunk_args(p, (const uint8_t*)d_in + r.t0 * row, row * n_time, (int32_t)r.len,
+                              valid[r.g] ? p->acc : nullptr, p->acc);
+            en.t_len = r.len;
+            en.plan = p;
+            es.push_back(en);
+            valid[r.g] = 1;
+            added[r.g] += r.len;
+        }
+        st = launch_entries(&tmp, es, cfg);
+        if (st != XCORR_OK) return st;
+    }
+    for (int g = 0; g < n_gates; ++g) {
+        plans[g]->acc_valid = valid[g];
+        plans[g]->samples += added[g];
+        plans[g]->total += added[g];
+    }
+    return XCORR_OK;
+}
+
 xcorr_status xcorr_batch_destroy(xcorr_batch_t b)
 {
     {

@@ -23,6 +23,8 @@ struct xcorr_plan_s {
     int xcd_map = 1;
     int tile = 0;                   // int8 tile variant in use
     int persist_grid = 0;           // persistent workgroups of the LDS-DMA variants, 0 = off
+    int* d_counters = nullptr;      // 8 work counters for batched launches over this plan
+    uint8_t* d_tile_sel = nullptr;  // tile selection of xcorr_dump_tiles (allocated on first use)
     int64_t fold_bound = 0;
     int64_t samples = 0;            // samples since the last reset
     int64_t window_start = 0;       // absolute sample index of the current window

@@ -34,7 +34,7 @@ EXPORTS = ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dum
            "xcorr_graph_launch", "xcorr_graph_destroy", "xcorr_batch_destroy",
            "xcorr_server_create", "xcorr_server_open", "xcorr_server_submit", "xcorr_server_poll",
            "xcorr_server_wait", "xcorr_server_close", "xcorr_server_query", "xcorr_server_destroy",
-           "xcorr_corner_turn")
+           "xcorr_corner_turn", "xcorr_dump_tiles", "xcorr_accumulate_gated")
 
 
 class PlanDesc(ctypes.Structure):
@@ -128,6 +128,8 @@ def _load():
     L.xcorr_server_query.argtypes = [vp, P(ServerStats)]
     L.xcorr_server_destroy.argtypes = [vp]
     L.xcorr_corner_turn.argtypes = [vp, vp, P(PacketLayout), i32, vp, vp]
+    L.xcorr_dump_tiles.argtypes = [vp, vp, vp, i32, P(DumpInfo)]
+    L.xcorr_accumulate_gated.argtypes = [P(vp), i32, vp, i64, vp]
     for name in EXPORTS:
         if name not in ("xcorr_strerror", "xcorr_last_error", "xcorr_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -248,6 +250,20 @@ class Plan:
         _check(lib.xcorr_accumulate_dump(self._h, ctypes.c_void_p(self._ptr(x) if t else 0), t,
                                          ctypes.c_void_p(self._ptr(out)), int(bool(reset)),
                                          ctypes.byref(info)))
+        return out, Dump(info.samples_accumulated, info.start_sample, info.n_dumps)
+
+    def dump_tiles(self, out: torch.Tensor, tile_select, reset: bool = True):
+        """Dump (and restart) only the selected 64 x 64 tiles; tile_select is a
+        sequence of nr (nr + 1) / 2 flags in lower-triangle tile order."""
+        self._check_output(out)
+        nr = (self.n_inputs + 63) // 64
+        sel = bytes(1 if v else 0 for v in tile_select)
+        if len(sel) != nr * (nr + 1) // 2:
+            raise ValueError("tile_select needs %d flags" % (nr * (nr + 1) // 2))
+        info = DumpInfo()
+        buf = (ctypes.c_uint8 * len(sel)).from_buffer_copy(sel)
+        _check(lib.xcorr_dump_tiles(self._h, ctypes.c_void_p(self._ptr(out)), ctypes.cast(buf, ctypes.c_void_p),
+                                    int(bool(reset)), ctypes.byref(info)))
         return out, Dump(info.samples_accumulated, info.start_sample, info.n_dumps)
 
     def query(self) -> PlanInfo:
@@ -514,3 +530,17 @@ def corner_turn(packets: torch.Tensor, n_fengines: int, inputs_per_feng: int, n_
                                  ctypes.byref(lay), FORMATS[out_fmt], ctypes.c_void_p(out.data_ptr()),
                                  ctypes.c_void_p(int(s.cuda_stream))))
     return out
+
+
+def accumulate_gated(plans, x: torch.Tensor, gate) -> None:
+    """Pulsar gating: sample t of x goes to plans[gate[t]] (255 = discarded)."""
+    t = plans[0]._check_input(x)
+    for p in plans[1:]:
+        p._check_input(x)
+    g = bytes(int(v) for v in gate)
+    if len(g) != t:
+        raise ValueError("one gate per sample")
+    hs = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    buf = (ctypes.c_uint8 * max(1, len(g))).from_buffer_copy(g if g else b"\0")
+    _check(lib.xcorr_accumulate_gated(hs, len(plans), ctypes.c_void_p(x.data_ptr() if t else 0), t,
+                                      ctypes.cast(buf, ctypes.c_void_p)))

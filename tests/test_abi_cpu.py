@@ -158,3 +158,21 @@ def test_server_calls_on_invalid_handles_and_arguments():
     assert L.xcorr_server_query(bogus, None) == -4
     assert L.xcorr_server_destroy(bogus) == -4
     assert L.xcorr_server_destroy(None) == -4
+
+
+def test_accumulate_variants_on_invalid_handles():
+    from paper_1401_8288_amd import xcorr
+    L = xcorr.lib
+    bogus = ctypes.c_void_p(0x1234)
+    plans = (ctypes.c_void_p * 2)(0x1234, 0x5678)
+    sel = (ctypes.c_uint8 * 1)(1)
+    assert L.xcorr_dump_tiles(bogus, None, ctypes.cast(sel, ctypes.c_void_p), 1, None) == -4
+    assert L.xcorr_accumulate_gated(None, 1, None, 0, None) == -1
+    assert L.xcorr_accumulate_gated(plans, 0, None, 0, None) == -1
+    assert L.xcorr_accumulate_gated(plans, 65, None, 0, None) == -1
+    assert L.xcorr_accumulate_gated(plans, 2, None, 0, None) == -4
+    lay = xcorr.PacketLayout(0, 1, 4, 1, 1)
+    assert L.xcorr_corner_turn(None, None, ctypes.byref(lay), 0, None, None) == -1
+    lay = xcorr.PacketLayout(1, 1, 6, 1, 1)
+    assert L.xcorr_corner_turn(None, None, ctypes.byref(lay), 0, None, None) == -6
+    assert L.xcorr_corner_turn(None, None, None, 0, None, None) == -1
