@@ -142,10 +142,12 @@ xcorr_status xcorr_dump_tiles(xcorr_plan_t plan, void* d_out, const uint8_t* til
  * layout of xcorr_accumulate) is integrated into plans[gate[t]]; gate is a
  * HOST array of n_time bytes, each < n_gates or 0xFF (sample discarded).
  * The plans (1..64, distinct) must share n_inputs, n_channels, format and
- * stream, and use the int8 path.  The runs of equal gate go out as batched
- * persistent launches, a round at a time (each round touches every gate's
- * accumulator at most once); runs much shorter than 64 samples waste MFMA
- * work on padding.  Dump each gate's plan with xcorr_dump. */
+ * stream; their paths may differ.  The samples of each gate are first packed
+ * together (one HBM pass over the kept samples, into a buffer the first plan
+ * holds and grows as needed: up to the window's size), then each gate with
+ * samples runs as the plan's own launch over its packed rows.  Waits for the
+ * plans' stream before the first launch (the sample lists are host
+ * temporaries).  Dump each gate's plan with xcorr_dump. */
 xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, const void* d_in, int64_t n_time,
                                     const uint8_t* gate);
 

@@ -313,13 +313,17 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
     return XCORR_OK;
 }
 
-// Runs the launches of one window.  If `final_dst` is non-null the last chunk
-// writes its result there instead of into the accumulator.
 xcorr_status run_window(xcorr_plan_t p, const void* d_in, int64_t n_time, void* final_dst)
 {
+    return run_window_strided(p, (const uint8_t*)d_in, row_bytes_of(p) * n_time, n_time, final_dst);
+}
+
+}  // namespace
+
+xcorr_status xcorr::run_window_strided(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride,
+                                       int64_t n_time, void* final_dst)
+{
     const int64_t row = row_bytes_of(p);
-    const int64_t chan_stride = row * n_time;
-    const uint8_t* in = (const uint8_t*)d_in;
     for (int64_t t0 = 0; t0 < n_time; t0 += p->fold_bound) {
         const int64_t len = std::min<int64_t>(p->fold_bound, n_time - t0);
         const bool last = t0 + len >= n_time;
@@ -331,8 +335,6 @@ xcorr_status run_window(xcorr_plan_t p, const void* d_in, int64_t n_time, void* 
     }
     return XCORR_OK;
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -585,6 +587,8 @@ xcorr_status xcorr_destroy(xcorr_plan_t p)
     release(p->d_items);
     release(p->d_counters);
     release(p->d_tile_sel);
+    release(p->d_gate_buf);
+    release(p->d_gate_idx);
     delete p;
     if (e != hipSuccess) return hip_fail(e, "destroy: stream synchronize");
     return XCORR_OK;

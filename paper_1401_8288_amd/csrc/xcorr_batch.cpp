@@ -2,6 +2,7 @@
 // subarrays, the autotuner that picks the launch configuration, and hipGraph
 // capture of a whole integration step.  See include/xcorr.h.
 #include "xcorr_host.h"
+#include "xcorr_gate.h"
 
 #include <algorithm>
 #include <cstring>
@@ -453,8 +454,6 @@ xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, 
         if (!plan_live(plans[g])) return fail(XCORR_ERR_STATE, "gate plan %d is not valid", g);
         const xcorr_plan_s* p = plans[g];
         const xcorr_plan_s* p0 = plans[0];
-        if (p->d.path != XCORR_PATH_I8_MFMA || p->tile == kTileW4)
-            return fail(XCORR_ERR_UNSUPPORTED, "gated accumulation runs the batched int8 path");
         if (p->d.n_inputs != p0->d.n_inputs || p->d.n_channels != p0->d.n_channels || p->d.format != p0->d.format ||
             p->stream != p0->stream)
             return fail(XCORR_ERR_ARG, "gate plans must share inputs, channels, format and stream");
@@ -468,57 +467,73 @@ xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, 
     for (int64_t t = 0; t < n_time; ++t)
         if (gate[t] != 0xFF && gate[t] >= n_gates) return fail(XCORR_ERR_ARG, "gate[%lld] out of range", (long long)t);
 
-    // runs of equal gate, split at the fold bound; the k-th run of a gate
-    // goes into round k so that a round touches each accumulator once
-    struct Run { int g; int64_t t0, len; };
-    std::vector<std::vector<Run>> rounds;
-    std::vector<int> count(n_gates, 0);
-    for (int64_t t = 0; t < n_time;) {
-        int64_t e = t + 1;
-        while (e < n_time && gate[e] == gate[t]) ++e;
-        if (gate[t] != 0xFF) {
-            const int g = gate[t];
-            for (int64_t c = t; c < e; c += plans[g]->fold_bound) {
-                const int k = count[g]++;
-                if ((int)rounds.size() <= k) rounds.resize(k + 1);
-                rounds[k].push_back(Run{g, c, std::min<int64_t>(plans[g]->fold_bound, e - c)});
-            }
-        }
-        t = e;
-    }
+    // The samples of each gate are gathered, in time order, into one packed
+    // buffer [channel][kept sample][input] held by the first plan (gate g
+    // occupies rows off[g] .. off[g] + n[g]); then every gate's plan
+    // accumulates its rows, all gates in one batched launch per fold chunk.
     xcorr_plan_s* p0 = plans[0];
-    xcorr_batch_s tmp;
-    tmp.plans.assign(plans, plans + n_gates);
-    tmp.stream = p0->stream;
-    tmp.format = p0->d.format;
-    tmp.d_counters = p0->d_counters;
-    const bool dma = p0->d.format == XCORR_CI4 && p0->d.n_inputs % 16 == 0 && p0->tile != kTileRegs;
-    const xcorr_batch_config cfg{dma ? (p0->tile == kTileDma8 ? kTileDma8 : kTileDma4) : kTileRegs,
-                                 p0->persist_grid ? p0->persist_grid : 256, 1, 0};
+    std::vector<int32_t> idx;
+    std::vector<int64_t> off(n_gates, 0), cnt(n_gates, 0);
+    for (int64_t t = 0; t < n_time; ++t)
+        if (gate[t] != 0xFF) cnt[gate[t]] += 1;
+    int64_t kept = 0;
+    for (int g = 0; g < n_gates; ++g) {
+        off[g] = kept;
+        kept += cnt[g];
+    }
+    if (kept == 0) return XCORR_OK;
+    if (kept > 0x7fffffff) return fail(XCORR_ERR_UNSUPPORTED, "window too long for gating");
+    idx.resize(kept);
+    {
+        std::vector<int64_t> pos(off);
+        for (int64_t t = 0; t < n_time; ++t)
+            if (gate[t] != 0xFF) idx[pos[gate[t]]++] = (int32_t)t;
+    }
     const int64_t row = row_bytes_of(p0);
-    std::vector<char> valid(n_gates);
-    for (int g = 0; g < n_gates; ++g) valid[g] = plans[g]->acc_valid;
-    std::vector<int64_t> added(n_gates, 0);
-    for (const std::vector<Run>& round : rounds) {
-        std::vector<Entry> es;
-        for (const Run& r : round) {
-            xcorr_plan_s* p = plans[r.g];
-            Entry en;
-            en.a = chunk_args(p, (const uint8_t*)d_in + r.t0 * row, row * n_time, (int32_t)r.len,
-                              valid[r.g] ? p->acc : nullptr, p->acc);
-            en.t_len = r.len;
-            en.plan = p;
-            es.push_back(en);
-            valid[r.g] = 1;
-            added[r.g] += r.len;
+    const size_t need = (size_t)kept * row * p0->d.n_channels;
+    hipError_t e = hipSuccess;
+    if (p0->gate_buf_bytes < need) {
+        e = hipStreamSynchronize(p0->stream);
+        if (e == hipSuccess) {
+            if (p0->d_gate_buf) (void)hipFree(p0->d_gate_buf);
+            p0->d_gate_buf = nullptr;
+            p0->gate_buf_bytes = 0;
+            e = hipMalloc(&p0->d_gate_buf, need);
+            if (e == hipSuccess) p0->gate_buf_bytes = need;
         }
-        st = launch_entries(&tmp, es, cfg);
+    }
+    if (e == hipSuccess && p0->gate_idx_bytes < (size_t)kept * 4) {
+        e = hipStreamSynchronize(p0->stream);
+        if (e == hipSuccess) {
+            if (p0->d_gate_idx) (void)hipFree(p0->d_gate_idx);
+            p0->d_gate_idx = nullptr;
+            p0->gate_idx_bytes = 0;
+            e = hipMalloc((void**)&p0->d_gate_idx, (size_t)kept * 4);
+            if (e == hipSuccess) p0->gate_idx_bytes = (size_t)kept * 4;
+        }
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(XCORR_ERR_NOMEM, "gating buffers: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpyAsync(p0->d_gate_idx, idx.data(), (size_t)kept * 4, hipMemcpyHostToDevice, p0->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p0->stream);   // idx is a host temporary
+    if (e == hipSuccess)
+        e = launch_gather_rows(p0->d_gate_buf, d_in, p0->d_gate_idx, kept, n_time, row, p0->d.n_channels, p0->stream);
+    if (e != hipSuccess) return hip_fail(e, "gate gather");
+
+    // One launch (per fold chunk) per gate, each over all channels: a gate
+    // with few samples is bound by its accumulator's read and write, and a
+    // launch of its own spreads that traffic over the whole chip.
+    const uint8_t* packed = (const uint8_t*)p0->d_gate_buf;
+    for (int g = 0; g < n_gates; ++g) {
+        if (cnt[g] == 0) continue;
+        st = run_window_strided(plans[g], packed + off[g] * row, row * kept, cnt[g], nullptr);
         if (st != XCORR_OK) return st;
     }
     for (int g = 0; g < n_gates; ++g) {
-        plans[g]->acc_valid = valid[g];
-        plans[g]->samples += added[g];
-        plans[g]->total += added[g];
+        plans[g]->samples += cnt[g];
+        plans[g]->total += cnt[g];
     }
     return XCORR_OK;
 }

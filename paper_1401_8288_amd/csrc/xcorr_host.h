@@ -25,6 +25,10 @@ struct xcorr_plan_s {
     int persist_grid = 0;           // persistent workgroups of the LDS-DMA variants, 0 = off
     int* d_counters = nullptr;      // 8 work counters for batched launches over this plan
     uint8_t* d_tile_sel = nullptr;  // tile selection of xcorr_dump_tiles (allocated on first use)
+    void* d_gate_buf = nullptr;     // gated accumulation: packed samples of all gates (grows on use)
+    size_t gate_buf_bytes = 0;
+    int32_t* d_gate_idx = nullptr;  // ... and their source sample indices
+    size_t gate_idx_bytes = 0;
     int64_t fold_bound = 0;
     int64_t samples = 0;            // samples since the last reset
     int64_t window_start = 0;       // absolute sample index of the current window
@@ -43,6 +47,12 @@ int64_t row_bytes_of(const xcorr_plan_s* p);
 LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
                       const void* src, void* dst);
 void fill_info(const xcorr_plan_s* p, xcorr_dump_info* info);
+// Enqueues the launches that accumulate n_time samples of every channel
+// (channel c's rows start at in + c * chan_stride), split at the fold bound.
+// If final_dst is non-null the last launch writes its result there instead
+// of into the accumulator.
+xcorr_status run_window_strided(xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int64_t n_time,
+                                void* final_dst);
 // Relative cost of a work item (MFMA blocks its waves own).
 int item_blocks(const WorkItem& it);
 // One fused window (accumulate + dump with reset) for each plan, all in one

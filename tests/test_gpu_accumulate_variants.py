@@ -62,6 +62,26 @@ def test_gated_accumulation_matches_oracle(n_in, fmt):
         p.close()
 
 
+def test_gates_may_run_different_paths():
+    # CI4 products summed over 3000 samples stay below 2^24: the float paths
+    # are exact here
+    say("gating across paths")
+    X = xc()
+    n_ch, n_t, n_in = 3, 3000, 40
+    x = synth.random_input(n_ch, n_t, n_in, "ci4", seed=8, device=DEV)
+    g = pulsar_gates(n_t, 256)
+    plans = [X.Plan(n_in, n_ch, "ci4", path) for path in ("f32", "i8", "f16")]
+    X.accumulate_gated(plans, x, g)
+    a = x.cpu().numpy()
+    for k, p in enumerate(plans):
+        out, _ = p.dump()
+        torch.cuda.synchronize()
+        ref = oracle.correlate(a[:, g == k], "ci4")
+        got = out.cpu().numpy()
+        np.testing.assert_array_equal(got, ref.astype(got.dtype), err_msg="gate %d" % k)
+        p.close()
+
+
 def test_gating_with_every_sample_in_one_gate_equals_plain_accumulation():
     X = xc()
     x = synth.random_input(3, 1000, 128, "ci4", seed=5, device=DEV)
@@ -74,6 +94,18 @@ def test_gating_with_every_sample_in_one_gate_equals_plain_accumulation():
     assert int(out0.abs().sum()) == 0
     with pytest.raises(X.XcorrError):
         X.accumulate_gated([p0, p1], x, np.full(1000, 2, dtype=np.uint8))   # gate out of range
+
+
+def test_gating_that_discards_every_sample_leaves_the_gates_empty():
+    X = xc()
+    x = synth.random_input(2, 400, 64, "ci4", seed=6, device=DEV)
+    plans = [X.Plan(64, 2, "ci4", "i8") for _ in range(2)]
+    X.accumulate_gated(plans, x, np.full(400, 255, dtype=np.uint8))
+    for p in plans:
+        out, info = p.dump()
+        torch.cuda.synchronize()
+        assert int(out.abs().sum()) == 0 and info.samples_accumulated == 0
+        p.close()
 
 
 def tile_of(n_in):
