@@ -23,6 +23,13 @@ Contents
                     unpacker pads 4 to 8 bits and reorders the channels of
                     the F-engines next to each other; packet-format figure:
                     the spectra of a packet follow one another).
+  pfb_frames,    -- the F-stage of Sec. 2.3 (and Sec. 4: 2 taps, 8192
+  pfb_spectra,      points, 8-bit real ADC samples): polyphase filter bank
+  requantise4,      (weighted sum of consecutive frames, then a real DFT
+  fstage            whose first N/2 bins are the channels), equalisation by
+                    a real gain per input and channel, requantisation to 4+4
+                    bits, and selection of a contiguous run of channels,
+                    written in X-stage order.
 
 Formats: "ci4" = one byte per sample, high nibble real, low nibble imaginary,
 two's complement (Sec. 2.3: 4 bits real and 4 bits imaginary); "ci8" = two
@@ -263,3 +270,61 @@ def corner_turn(packets: np.ndarray, n_fengines: int, inputs_per_feng: int, n_ch
     re = x.view(np.int8) >> 4
     im = (x << 4).view(np.int8) >> 4
     return np.stack([re, im], axis=-1).astype(np.int8)
+
+
+# ---------------------------------------------------------------- F-stage
+
+def pfb_frames(adc: np.ndarray, coeff: np.ndarray, n_points: int, n_taps: int) -> np.ndarray:
+    """Polyphase filter-bank front end (Sec. 2.3: the first F-stage operation).
+
+    adc: int8 [n_inputs][n_samples] real samples; coeff: [n_taps * n_points]
+    prototype filter.  Spectrum m of an input uses frames m .. m + P - 1 of N
+    samples: y_m[j] = sum_p coeff[p N + j] * x[(m + p) N + j] (fp64).
+    Returns [n_inputs][n_spectra][N], n_spectra = n_samples // N - P + 1.
+    """
+    N, P = n_points, n_taps
+    x = np.asarray(adc).astype(np.float64)
+    n_spec = x.shape[1] // N - P + 1
+    if n_spec <= 0:
+        return np.zeros((x.shape[0], 0, N))
+    frames = x[:, :(n_spec + P - 1) * N].reshape(x.shape[0], n_spec + P - 1, N)
+    h = np.asarray(coeff, dtype=np.float64).reshape(P, N)
+    y = np.zeros((x.shape[0], n_spec, N))
+    for p in range(P):
+        y += frames[:, p:p + n_spec, :] * h[p]
+    return y
+
+
+def pfb_spectra(adc: np.ndarray, coeff: np.ndarray, n_points: int, n_taps: int) -> np.ndarray:
+    """Channelised spectra: X_m[k] = sum_j y_m[j] exp(-2 pi i j k / N) for the
+    N/2 channels k = 0 .. N/2 - 1 of the real input (Sec. 2.3; Sec. 4: an
+    8192-point transform of the 200 MHz samples gives 24.4 kHz channels).
+    complex128 [n_inputs][n_spectra][N/2]."""
+    y = pfb_frames(adc, coeff, n_points, n_taps)
+    return np.fft.fft(y, axis=-1)[..., :n_points // 2]
+
+
+def requantise4(v: np.ndarray) -> np.ndarray:
+    """4-bit requantisation of one component (Sec. 2.3): round half to even,
+    then saturate to the symmetric range [-7, 7] (int8 result)."""
+    return np.clip(np.rint(v), -7, 7).astype(np.int8)
+
+
+def fstage(adc: np.ndarray, coeff: np.ndarray, gain: np.ndarray, n_points: int, n_taps: int,
+           chan_begin: int, n_chan: int, out: str = "ci4") -> np.ndarray:
+    """The F-stage feeding the X-stage (Sec. 2.3): PFB spectra, equalisation
+    v = gain[a][c - chan_begin] * X_m[c] for the selected channels
+    c = chan_begin .. chan_begin + n_chan - 1, then 4+4-bit requantisation.
+
+    out "ci4": uint8 [n_chan][n_spectra][n_inputs], high nibble = real, low
+    nibble = imaginary (the X-stage input layout); out "c128": the equalised
+    values before requantisation, complex128 [n_chan][n_spectra][n_inputs].
+    """
+    X = pfb_spectra(adc, coeff, n_points, n_taps)[..., chan_begin:chan_begin + n_chan]
+    v = X * np.asarray(gain, dtype=np.float64)[:, None, :]
+    v = np.ascontiguousarray(v.transpose(2, 1, 0))
+    if out == "c128":
+        return v
+    re = requantise4(v.real).astype(np.uint8)
+    im = requantise4(v.imag).astype(np.uint8)
+    return ((re & 0xF) << 4) | (im & 0xF)

@@ -255,3 +255,62 @@ def random_input(n_channels: int, n_time: int, n_inputs: int, fmt: str, seed: in
     re = torch.randint(lo, hi + 1, shape, generator=g, device=device)
     im = torch.randint(lo, hi + 1, shape, generator=g, device=device)
     return pack_ci4(re, im) if fmt == "ci4" else pack_ci8(re, im)
+
+
+# ------------------------------------------------------------------ F-stage inputs
+#
+# The F-stage of Sec. 2.3 takes 8-bit real ADC samples (Sec. 4: 200 MHz clock)
+# through a 2-tap, 8192-point PFB.  The prototype filter and the equaliser
+# gains are inputs of that stage, drawn here like the samples.
+
+def pfb_coefficients(n_taps: int = 2, n_points: int = PFB_POINTS) -> torch.Tensor:
+    """Prototype filter of P taps x N points: a sinc whose main lobe spans one
+    channel, times a Hamming window over the P N coefficients (float32, CPU).
+    The paper gives the taps and points only; this shape is the usual one for
+    critically sampled PFBs."""
+    P, N = n_taps, n_points
+    k = torch.arange(P * N, dtype=torch.float64)
+    u = (k + 0.5) / N - P / 2.0
+    ham = 0.54 - 0.46 * torch.cos(2.0 * math.pi * k / max(P * N - 1, 1))
+    return (torch.sinc(u) * ham).to(torch.float32)
+
+
+def adc_input(n_inputs: int, n_samples: int, seed: int, sigma: float = 16.0, rho: float = 0.05,
+              tone_amp: float = 0.0, tone_hz: float = 0.0, device="cpu", out: torch.Tensor | None = None):
+    """Real int8 ADC streams [n_inputs][n_samples]: per input, independent
+    Gaussian noise plus a common sky signal (fraction rho of the power) delayed
+    by 0..15 samples per input, plus an optional common tone, rounded half to
+    even and clipped to [-128, 127]."""
+    if out is None:
+        out = torch.empty((n_inputs, n_samples), dtype=torch.int8, device=device)
+    elif tuple(out.shape) != (n_inputs, n_samples) or out.dtype != torch.int8:
+        raise ValueError("output buffer has the wrong shape or dtype")
+    dev = out.device
+    g = torch.Generator(device=dev).manual_seed(seed * 7_654_321 + 11)
+    common = torch.randn(n_samples + 16, generator=g, device=dev, dtype=torch.float32)
+    gd = torch.Generator(device="cpu").manual_seed(seed + 99)
+    delays = torch.randint(0, 16, (n_inputs,), generator=gd)
+    t = torch.arange(n_samples, device=dev, dtype=torch.float64)
+    tone = (tone_amp * torch.cos(2.0 * math.pi * tone_hz / ADC_CLOCK_HZ * t)).to(torch.float32) \
+        if tone_amp else None
+    a_n, a_c = sigma * math.sqrt(1.0 - rho), sigma * math.sqrt(rho)
+    for a in range(n_inputs):
+        ga = torch.Generator(device=dev).manual_seed(seed * 1_000_003 + 31 * a + 5)
+        v = a_n * torch.randn(n_samples, generator=ga, device=dev, dtype=torch.float32)
+        d = int(delays[a])
+        v += a_c * common[16 - d:16 - d + n_samples]
+        if tone is not None:
+            v += tone
+        out[a] = torch.clamp(torch.round(v), -128, 127).to(torch.int8)
+    return out
+
+
+def fstage_gains(n_inputs: int, n_chan: int, coeff: torch.Tensor, sigma: float = 16.0,
+                 target: float = 2.5, seed: int = 0) -> torch.Tensor:
+    """Equaliser gains [n_inputs][n_chan] (float32, CPU) that bring white
+    noise of rms sigma to rms `target` per component after the PFB, with a
+    +-10 % spread per input and channel (a bandpass to flatten)."""
+    norm = sigma * math.sqrt(float((coeff.double() ** 2).sum()) / 2.0)
+    g = torch.Generator(device="cpu").manual_seed(seed + 4242)
+    spread = 1.0 + 0.1 * (2.0 * torch.rand((n_inputs, n_chan), generator=g, dtype=torch.float64) - 1.0)
+    return (target / norm * spread).to(torch.float32)
