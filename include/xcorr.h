@@ -192,6 +192,48 @@ xcorr_status xcorr_corner_turn(const void* d_packets, const uint8_t* d_valid, co
                                int32_t out_format, void* d_out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * F-stage (Sec. 2.3; Sec. 4: 8-bit real ADC samples at 200 MHz, a 2-tap
+ * 8192-point polyphase filter bank, equalisation, 4+4-bit requantisation and
+ * a contiguous run of channels), producing the X-stage input directly.
+ *
+ * For input a and spectrum m (N = n_points, P = n_taps):
+ *   y[j]  = sum_{p<P} coeff[p N + j] * adc[a][(m + p) N + j],   j < N
+ *   X[k]  = sum_j y[j] e^{-2 pi i j k / N},   channels k < N / 2
+ *   v     = gain[a][k - chan_begin] * X[k]   for the kept channels
+ *   CI4:  each component rounded half to even, saturated to [-7, 7], packed
+ *         high nibble = real, low nibble = imaginary (two's complement)
+ * n_spectra = n_samples / N - P + 1 (none if below 1); a stream continues
+ * across calls when the caller keeps the last (P - 1) N samples in front.
+ *
+ *   d_adc      device, int8 [n_inputs][adc_stride], first n_samples used;
+ *              adc_stride even
+ *   d_coeff    device, float [P * N] prototype filter
+ *   d_gain     device, float [n_inputs][n_chan]
+ *   d_out      device; XCORR_FSTAGE_CI4: uint8 [n_chan][n_spectra][n_inputs],
+ *              the layout xcorr_accumulate reads;
+ *              XCORR_FSTAGE_F32: float [n_chan][n_spectra][n_inputs][2], the
+ *              equalised values before requantisation
+ *   n_spectra  host, optional: receives n_spectra
+ * Device pointers 16-byte aligned.  N must be 8192 and P 1 or 2
+ * (XCORR_ERR_UNSUPPORTED otherwise).  fp32 arithmetic.  Enqueued on
+ * `stream`; nothing is allocated.
+ * ------------------------------------------------------------------------ */
+#define XCORR_FSTAGE_CI4 0
+#define XCORR_FSTAGE_F32 1
+
+typedef struct {
+    int32_t n_inputs;    /* ADC streams                                 */
+    int32_t n_points;    /* N, transform length (8192)                  */
+    int32_t n_taps;      /* P, filter-bank taps (1 or 2)                */
+    int32_t chan_begin;  /* first kept channel                          */
+    int32_t n_chan;      /* kept channels, chan_begin + n_chan <= N / 2 */
+    int32_t out_kind;    /* XCORR_FSTAGE_CI4 or XCORR_FSTAGE_F32        */
+} xcorr_fstage_desc;
+
+xcorr_status xcorr_fstage(const xcorr_fstage_desc* desc, const void* d_adc, int64_t adc_stride, int64_t n_samples,
+                          const float* d_coeff, const float* d_gain, void* d_out, int64_t* n_spectra, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batches: several plans (subarrays of uneven input and channel counts, the
  * X-stage of several arrays sharing one GPU, Sec. 3) run as ONE persistent
  * launch per time chunk.  Every plan of a batch must use XCORR_PATH_I8_MFMA

@@ -2,6 +2,7 @@
 // and the launch sequence of accumulate / dump.  See include/xcorr.h.
 #include "xcorr_host.h"
 #include "xcorr_ct.h"
+#include "xcorr_fstage.h"
 #include "xcorr_tiles.h"
 
 #include <algorithm>
@@ -573,6 +574,46 @@ xcorr_status xcorr_corner_turn(const void* d_packets, const uint8_t* d_valid, co
     a.n_time = (int64_t)L->n_blocks * L->spectra_per_packet;
     hipError_t e = launch_corner_turn(a, out_format, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "corner turn launch");
+    return XCORR_OK;
+}
+
+xcorr_status xcorr_fstage(const xcorr_fstage_desc* d, const void* d_adc, int64_t adc_stride, int64_t n_samples,
+                          const float* d_coeff, const float* d_gain, void* d_out, int64_t* n_spectra, void* stream)
+{
+    if (!d) return fail(XCORR_ERR_ARG, "null descriptor");
+    if (d->n_inputs < 1 || d->n_chan < 1) return fail(XCORR_ERR_ARG, "n_inputs and n_chan must be >= 1");
+    if (d->n_points != 8192) return fail(XCORR_ERR_UNSUPPORTED, "n_points must be 8192");
+    if (d->n_taps != 1 && d->n_taps != 2) return fail(XCORR_ERR_UNSUPPORTED, "n_taps must be 1 or 2");
+    if (d->chan_begin < 0 || (int64_t)d->chan_begin + d->n_chan > d->n_points / 2)
+        return fail(XCORR_ERR_ARG, "channels [%d, %d) outside [0, %d)", d->chan_begin, d->chan_begin + d->n_chan,
+                    d->n_points / 2);
+    if (d->out_kind != XCORR_FSTAGE_CI4 && d->out_kind != XCORR_FSTAGE_F32)
+        return fail(XCORR_ERR_ARG, "unknown out_kind %d", d->out_kind);
+    if (n_samples < 0 || adc_stride < n_samples || adc_stride % 2)
+        return fail(XCORR_ERR_ARG, "need 0 <= n_samples <= adc_stride and an even adc_stride");
+    const int64_t n_spec = std::max<int64_t>(0, n_samples / d->n_points - d->n_taps + 1);
+    if (n_spec > 0x7fffffff) return fail(XCORR_ERR_UNSUPPORTED, "too many spectra");
+    if (n_spectra) *n_spectra = n_spec;
+    if (n_spec == 0) return XCORR_OK;
+    xcorr_status s = check_ptr(d_adc, "d_adc");
+    if (s == XCORR_OK) s = check_ptr(d_coeff, "d_coeff");
+    if (s == XCORR_OK) s = check_ptr(d_gain, "d_gain");
+    if (s == XCORR_OK) s = check_ptr(d_out, "d_out");
+    if (s != XCORR_OK) return s;
+    FstageArgs a{};
+    a.adc = (const int8_t*)d_adc;
+    a.adc_stride = adc_stride;
+    a.coeff = d_coeff;
+    a.gain = d_gain;
+    a.out = d_out;
+    a.n_inputs = d->n_inputs;
+    a.n_taps = d->n_taps;
+    a.n_spectra = (int32_t)n_spec;
+    a.chan_begin = d->chan_begin;
+    a.n_chan = d->n_chan;
+    a.out_kind = d->out_kind;
+    hipError_t e = launch_fstage(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "F-stage launch");
     return XCORR_OK;
 }
 

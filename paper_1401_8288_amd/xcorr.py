@@ -34,7 +34,7 @@ EXPORTS = ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dum
            "xcorr_graph_launch", "xcorr_graph_destroy", "xcorr_batch_destroy",
            "xcorr_server_create", "xcorr_server_open", "xcorr_server_submit", "xcorr_server_poll",
            "xcorr_server_wait", "xcorr_server_close", "xcorr_server_query", "xcorr_server_destroy",
-           "xcorr_corner_turn", "xcorr_dump_tiles", "xcorr_accumulate_gated")
+           "xcorr_corner_turn", "xcorr_dump_tiles", "xcorr_accumulate_gated", "xcorr_fstage")
 
 
 class PlanDesc(ctypes.Structure):
@@ -86,6 +86,14 @@ class PacketLayout(ctypes.Structure):
                 ("spectra_per_packet", ctypes.c_int32)]
 
 
+class FstageDesc(ctypes.Structure):
+    _fields_ = [("n_inputs", ctypes.c_int32), ("n_points", ctypes.c_int32), ("n_taps", ctypes.c_int32),
+                ("chan_begin", ctypes.c_int32), ("n_chan", ctypes.c_int32), ("out_kind", ctypes.c_int32)]
+
+
+FSTAGE_CI4, FSTAGE_F32 = 0, 1
+
+
 class XcorrError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("xcorr status %d: %s" % (status, message))
@@ -130,6 +138,7 @@ def _load():
     L.xcorr_corner_turn.argtypes = [vp, vp, P(PacketLayout), i32, vp, vp]
     L.xcorr_dump_tiles.argtypes = [vp, vp, vp, i32, P(DumpInfo)]
     L.xcorr_accumulate_gated.argtypes = [P(vp), i32, vp, i64, vp]
+    L.xcorr_fstage.argtypes = [P(FstageDesc), vp, i64, i64, vp, vp, vp, P(i64), vp]
     for name in EXPORTS:
         if name not in ("xcorr_strerror", "xcorr_last_error", "xcorr_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -544,3 +553,39 @@ def accumulate_gated(plans, x: torch.Tensor, gate) -> None:
     buf = (ctypes.c_uint8 * max(1, len(g))).from_buffer_copy(g if g else b"\0")
     _check(lib.xcorr_accumulate_gated(hs, len(plans), ctypes.c_void_p(x.data_ptr() if t else 0), t,
                                       ctypes.cast(buf, ctypes.c_void_p)))
+
+
+def fstage(adc: torch.Tensor, coeff: torch.Tensor, gain: torch.Tensor, chan_begin: int, n_chan: int,
+           n_taps: int = 2, n_points: int = 8192, out_kind: str = "ci4", n_samples: int | None = None,
+           out: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """F-stage: int8 ADC samples [n_inputs][stride] -> X-stage input (see xcorr_fstage).
+
+    Returns uint8 [n_chan][n_spectra][n_inputs] ("ci4") or float32
+    [n_chan][n_spectra][n_inputs][2] ("f32")."""
+    if adc.dtype != torch.int8 or adc.dim() != 2 or adc.stride(1) != 1 or not adc.is_cuda:
+        raise ValueError("adc must be an int8 device tensor [n_inputs][samples] with unit sample stride")
+    n_in = adc.shape[0]
+    n_samples = adc.shape[1] if n_samples is None else n_samples
+    for name, t in (("coeff", coeff), ("gain", gain)):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device != adc.device:
+            raise ValueError("%s must be a contiguous float32 tensor on the ADC's device" % name)
+    if coeff.numel() != n_taps * n_points or gain.numel() != n_in * n_chan:
+        raise ValueError("coeff must hold n_taps * n_points values and gain n_inputs * n_chan")
+    n_spec = max(0, n_samples // n_points - n_taps + 1)
+    kind = {"ci4": FSTAGE_CI4, "f32": FSTAGE_F32}[out_kind]
+    shape = (n_chan, n_spec, n_in) if kind == FSTAGE_CI4 else (n_chan, n_spec, n_in, 2)
+    dt = torch.uint8 if kind == FSTAGE_CI4 else torch.float32
+    if out is None:
+        out = torch.empty(shape, dtype=dt, device=adc.device)
+    elif tuple(out.shape) != shape or out.dtype != dt or not out.is_contiguous():
+        raise ValueError("output must be a contiguous %s tensor %s" % (dt, shape))
+    d = FstageDesc(n_in, n_points, n_taps, chan_begin, n_chan, kind)
+    got = ctypes.c_int64(-1)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.xcorr_fstage(ctypes.byref(d), ctypes.c_void_p(adc.data_ptr()), adc.stride(0), n_samples,
+                            ctypes.c_void_p(coeff.data_ptr()), ctypes.c_void_p(gain.data_ptr()),
+                            ctypes.c_void_p(out.data_ptr() if out.numel() else 0), ctypes.byref(got),
+                            ctypes.c_void_p(int(s.cuda_stream))))
+    if got.value != n_spec:
+        raise RuntimeError("spectra count mismatch")
+    return out

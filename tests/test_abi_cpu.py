@@ -176,3 +176,27 @@ def test_accumulate_variants_on_invalid_handles():
     lay = xcorr.PacketLayout(1, 1, 6, 1, 1)
     assert L.xcorr_corner_turn(None, None, ctypes.byref(lay), 0, None, None) == -6
     assert L.xcorr_corner_turn(None, None, None, 0, None, None) == -1
+
+
+def test_fstage_argument_checks():
+    from paper_1401_8288_amd import xcorr
+    L = xcorr.lib
+    n = ctypes.c_int64(-1)
+
+    def call(d, stride=16384, n_samples=16384):
+        return L.xcorr_fstage(ctypes.byref(d) if d is not None else None, None, stride, n_samples,
+                              None, None, None, ctypes.byref(n), None)
+
+    ok = dict(n_inputs=4, n_points=8192, n_taps=2, chan_begin=0, n_chan=16, out_kind=0)
+    assert call(None) == -1
+    assert call(xcorr.FstageDesc(**dict(ok, n_points=4096))) == -6
+    assert call(xcorr.FstageDesc(**dict(ok, n_taps=3))) == -6
+    assert call(xcorr.FstageDesc(**dict(ok, chan_begin=4090))) == -1
+    assert call(xcorr.FstageDesc(**dict(ok, n_chan=0))) == -1
+    assert call(xcorr.FstageDesc(**dict(ok, out_kind=7))) == -1
+    assert call(xcorr.FstageDesc(**ok), stride=16383, n_samples=100) == -1      # odd stride
+    assert call(xcorr.FstageDesc(**ok), stride=100, n_samples=16384) == -1      # stride < samples
+    # fewer than P frames: no spectrum, nothing touched, pointers not needed
+    assert call(xcorr.FstageDesc(**ok), n_samples=16383) == 0 and n.value == 0
+    # a full spectrum needs the device buffers
+    assert call(xcorr.FstageDesc(**ok)) == -1 and n.value == 1

@@ -1,0 +1,191 @@
+"""GPU F-stage (Sec. 2.3; Sec. 4: 2-tap 8192-point PFB of 8-bit real samples,
+4+4-bit requantisation, a contiguous run of channels) against the CPU oracle.
+
+Tolerance (fp32 path against the fp64 oracle).  The filter-bank sum of P
+terms has relative error below P u (u = 2^-24).  A radix-16 Cooley-Tukey
+transform in floating point with twiddles accurate to one rounding satisfies
+the norm-wise bound ||dX||_2 <= c log2(N) u ||X||_2 with a small constant c;
+for a real frame ||X||_2 = sqrt(N) ||y||_2 (Parseval), and the kept channels
+are part of that vector, so per frame and per input
+    sqrt(sum_kept |dX_k|^2) <= c log2(N) u sqrt(N) ||y||_2,    c = 8 here,
+which also bounds every single channel.  The equalised value carries the
+gain's factor.  Requantised codes must equal the oracle's wherever the
+oracle's value is farther than that bound from a rounding boundary (a
+half-integer) inside the unsaturated range; elsewhere either neighbouring code
+is correct.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1401_8288_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+N = 8192
+U = 2.0 ** -24
+C_BOUND = 8.0
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def xc():
+    from paper_1401_8288_amd import xcorr
+    return xcorr
+
+
+def case(n_in, n_spec, P, seed, extra=0, tone_hz=0.0, tone_amp=0.0):
+    # rows of a 16-byte multiple (the row stride must be even); a ragged
+    # sample count is a view of the first n_samples
+    n_samples = (n_spec + P - 1) * N + extra
+    stride = (n_samples + 15) // 16 * 16
+    adc = synth.adc_input(n_in, stride, seed, tone_amp=tone_amp, tone_hz=tone_hz, device=DEV)[:, :n_samples]
+    h = synth.pfb_coefficients(P, N)
+    return adc, h
+
+
+def frame_bound(adc_np, h, P, gain_abs_max):
+    """Per-(input, spectrum) bound on the equalised error, from ||y||_2."""
+    y = oracle.pfb_frames(adc_np, h.numpy().astype(np.float64), N, P)
+    ny = np.sqrt((y ** 2).sum(axis=-1))                         # [A][M]
+    return C_BOUND * math.log2(N) * U * math.sqrt(N) * ny * gain_abs_max
+
+
+def check_codes(got, v_ref, bound_am):
+    """got: uint8 [C][M][A]; v_ref: complex [C][M][A]; bound_am: [A][M]."""
+    b = bound_am.T[None, :, :]                                  # [1][M][A]
+    ok = np.ones(got.shape, dtype=bool)
+    amb = np.zeros(got.shape, dtype=bool)
+    for comp, shift in ((v_ref.real, 4), (v_ref.imag, 0)):
+        g = ((got >> shift) & 0xF).astype(np.int8)
+        g = np.where(g > 7, g - 16, g)
+        ref = oracle.requantise4(comp)
+        near = (np.abs(comp - (np.floor(comp) + 0.5)) <= b) & (np.abs(comp) < 7.5 + b)
+        amb |= near
+        ok &= np.where(near, np.abs(g.astype(int) - ref.astype(int)) <= 1, g == ref)
+    return ok, amb
+
+
+@pytest.mark.parametrize("n_in,n_spec,P,ch0,n_ch,extra", [
+    (16, 5, 2, 0, 4096, 0),        # full band, whole input group
+    (20, 4, 2, 1000, 1628, 333),   # the paper's 1628-channel sub-band, ragged inputs and samples
+    (3, 3, 1, 4000, 96, 8191),     # single tap, band edge, fewer inputs than a group
+    (48, 9, 2, 7, 9, 5),           # spectra past one workgroup's run, odd channel offset
+])
+def test_equalised_spectra_within_the_bound(n_in, n_spec, P, ch0, n_ch, extra):
+    say("fstage f32", n_in, n_spec, P, ch0, n_ch, extra)
+    X = xc()
+    adc, h = case(n_in, n_spec, P, seed=n_in + P, extra=extra)
+    gain = synth.fstage_gains(n_in, n_ch, h, seed=n_in)
+    out = X.fstage(adc, h.to(DEV), gain.to(DEV), ch0, n_ch, n_taps=P, out_kind="f32")
+    torch.cuda.synchronize()
+    assert out.shape == (n_ch, n_spec, n_in, 2)
+    a = adc.cpu().numpy()
+    ref = oracle.fstage(a, h.numpy().astype(np.float64), gain.numpy().astype(np.float64), N, P, ch0, n_ch,
+                        out="c128")
+    got = out.cpu().numpy().astype(np.float64)
+    d = (got[..., 0] - ref.real) ** 2 + (got[..., 1] - ref.imag) ** 2      # [C][M][A]
+    err = np.sqrt(d.sum(axis=0)).T                                          # [A][M]
+    bound = frame_bound(a, h, P, float(gain.abs().max()))
+    say("  worst error / bound = %.3g" % float((err / bound).max()))
+    assert (err <= bound).all()
+
+
+@pytest.mark.parametrize("n_in,n_spec,P,ch0,n_ch,extra", [
+    (16, 5, 2, 0, 4096, 0),
+    (20, 4, 2, 1000, 1628, 333),
+    (3, 3, 1, 4000, 96, 8191),
+    (48, 9, 2, 7, 9, 5),
+])
+def test_requantised_codes_match_the_oracle(n_in, n_spec, P, ch0, n_ch, extra):
+    say("fstage ci4", n_in, n_spec, P, ch0, n_ch, extra)
+    X = xc()
+    adc, h = case(n_in, n_spec, P, seed=7 * n_in + P, extra=extra)
+    gain = synth.fstage_gains(n_in, n_ch, h, seed=n_in + 1)
+    out = X.fstage(adc, h.to(DEV), gain.to(DEV), ch0, n_ch, n_taps=P)
+    torch.cuda.synchronize()
+    assert out.shape == (n_ch, n_spec, n_in) and out.dtype == torch.uint8
+    a = adc.cpu().numpy()
+    v = oracle.fstage(a, h.numpy().astype(np.float64), gain.numpy().astype(np.float64), N, P, ch0, n_ch,
+                      out="c128")
+    bound = frame_bound(a, h, P, float(gain.abs().max()))
+    ok, amb = check_codes(out.cpu().numpy(), v, bound)
+    ref = oracle.fstage(a, h.numpy().astype(np.float64), gain.numpy().astype(np.float64), N, P, ch0, n_ch)
+    differ = out.cpu().numpy() != ref
+    say("  ambiguous %d, differing %d of %d" % (int(amb.sum()), int(differ.sum()), amb.size))
+    assert ok.all()
+    # a value lands within the bound of a half-integer with probability about
+    # twice the bound, per component: the band holds what it should, no more
+    expected = 2 * 2 * float(bound.mean()) * amb.size
+    assert amb.sum() <= 2 * expected + 10
+    np.testing.assert_array_equal(out.cpu().numpy()[~amb], ref[~amb])
+
+
+def test_fstage_feeds_the_x_stage():
+    # F-stage codes straight into the X-stage; with no ambiguous code the
+    # visibilities equal the oracle's correlation of the oracle's codes
+    X = xc()
+    n_in, n_spec, P, ch0, n_ch = 32, 12, 2, 500, 40
+    adc, h = case(n_in, n_spec, P, seed=77)
+    gain = synth.fstage_gains(n_in, n_ch, h, seed=3)
+    x = X.fstage(adc, h.to(DEV), gain.to(DEV), ch0, n_ch, n_taps=P)
+    plan = X.Plan(n_in, n_ch, "ci4", "i8")
+    plan.accumulate(x)
+    vis, info = plan.dump()
+    torch.cuda.synchronize()
+    a = adc.cpu().numpy()
+    hd, gd = h.numpy().astype(np.float64), gain.numpy().astype(np.float64)
+    codes = oracle.fstage(a, hd, gd, N, P, ch0, n_ch)
+    _, amb = check_codes(x.cpu().numpy(), oracle.fstage(a, hd, gd, N, P, ch0, n_ch, out="c128"),
+                         frame_bound(a, h, P, float(gain.abs().max())))
+    assert info.samples_accumulated == n_spec
+    np.testing.assert_array_equal(vis.cpu().numpy(), oracle.correlate(x.cpu().numpy(), "ci4"))
+    if amb.sum() == 0:
+        np.testing.assert_array_equal(vis.cpu().numpy(), oracle.correlate(codes, "ci4"))
+    plan.close()
+
+
+def test_stream_continues_across_calls():
+    # two calls whose windows overlap by (P - 1) frames give the spectra of one call
+    X = xc()
+    n_in, P, ch0, n_ch = 16, 2, 0, 4096
+    adc, h = case(n_in, 7, P, seed=5)
+    gain = synth.fstage_gains(n_in, n_ch, h, seed=5).to(DEV)
+    hd = h.to(DEV)
+    whole = X.fstage(adc, hd, gain, ch0, n_ch)
+    first = X.fstage(adc[:, :4 * N].contiguous(), hd, gain, ch0, n_ch)
+    second = X.fstage(adc[:, 3 * N:].contiguous(), hd, gain, ch0, n_ch)
+    torch.cuda.synchronize()
+    assert first.shape[1] == 3 and second.shape[1] == 4
+    assert torch.equal(torch.cat([first, second], dim=1), whole)
+
+
+def test_strided_adc_rows():
+    X = xc()
+    n_in, P = 5, 2
+    big = synth.adc_input(n_in, 4 * N + 64, 9, device=DEV)
+    h = synth.pfb_coefficients(P, N)
+    gain = synth.fstage_gains(n_in, 64, h, seed=1).to(DEV)
+    view = big[:, :3 * N]                                     # row stride 4N + 64
+    a = X.fstage(view, h.to(DEV), gain, 100, 64)
+    b = X.fstage(view.contiguous(), h.to(DEV), gain, 100, 64)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_tone_lands_in_its_channel():
+    X = xc()
+    n_in, P, k0 = 16, 2, 2345
+    adc, h = case(n_in, 4, P, seed=2, tone_hz=k0 * synth.CHANNEL_WIDTH_HZ, tone_amp=30.0)
+    gain = synth.fstage_gains(n_in, 4096, h, seed=2)
+    out = X.fstage(adc, h.to(DEV), gain.to(DEV), 0, 4096, out_kind="f32")
+    torch.cuda.synchronize()
+    p = (out.double() ** 2).sum(dim=-1).mean(dim=(1, 2))
+    assert int(torch.argmax(p)) == k0
