@@ -213,6 +213,10 @@ xcorr_status xcorr_corner_turn(const void* d_packets, const uint8_t* d_valid, co
  *              the layout xcorr_accumulate reads;
  *              XCORR_FSTAGE_F32: float [n_chan][n_spectra][n_inputs][2], the
  *              equalised values before requantisation
+ *   d_work     device scratch of xcorr_fstage_work_bytes bytes (CI4 output:
+ *              the codes in input-major order before the transpose into
+ *              X-stage order); may be NULL for F32.  Caller-owned, contents
+ *              undefined afterwards; calls that share it must not overlap.
  *   n_spectra  host, optional: receives n_spectra
  * Device pointers 16-byte aligned.  N must be 8192 and P 1 or 2
  * (XCORR_ERR_UNSUPPORTED otherwise).  fp32 arithmetic.  Enqueued on
@@ -231,7 +235,12 @@ typedef struct {
 } xcorr_fstage_desc;
 
 xcorr_status xcorr_fstage(const xcorr_fstage_desc* desc, const void* d_adc, int64_t adc_stride, int64_t n_samples,
-                          const float* d_coeff, const float* d_gain, void* d_out, int64_t* n_spectra, void* stream);
+                          const float* d_coeff, const float* d_gain, void* d_work, void* d_out, int64_t* n_spectra,
+                          void* stream);
+
+/* Bytes of d_work that xcorr_fstage needs for this descriptor and sample
+ * count (0 for F32 output). */
+xcorr_status xcorr_fstage_work_bytes(const xcorr_fstage_desc* desc, int64_t n_samples, size_t* bytes);
 
 /* ------------------------------------------------------------------------
  * Batches: several plans (subarrays of uneven input and channel counts, the

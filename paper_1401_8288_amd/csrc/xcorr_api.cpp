@@ -577,8 +577,9 @@ xcorr_status xcorr_corner_turn(const void* d_packets, const uint8_t* d_valid, co
     return XCORR_OK;
 }
 
-xcorr_status xcorr_fstage(const xcorr_fstage_desc* d, const void* d_adc, int64_t adc_stride, int64_t n_samples,
-                          const float* d_coeff, const float* d_gain, void* d_out, int64_t* n_spectra, void* stream)
+namespace {
+
+xcorr_status check_fstage_desc(const xcorr_fstage_desc* d, int64_t adc_stride, int64_t n_samples, int64_t* n_spec)
 {
     if (!d) return fail(XCORR_ERR_ARG, "null descriptor");
     if (d->n_inputs < 1 || d->n_chan < 1) return fail(XCORR_ERR_ARG, "n_inputs and n_chan must be >= 1");
@@ -591,14 +592,38 @@ xcorr_status xcorr_fstage(const xcorr_fstage_desc* d, const void* d_adc, int64_t
         return fail(XCORR_ERR_ARG, "unknown out_kind %d", d->out_kind);
     if (n_samples < 0 || adc_stride < n_samples || adc_stride % 2)
         return fail(XCORR_ERR_ARG, "need 0 <= n_samples <= adc_stride and an even adc_stride");
-    const int64_t n_spec = std::max<int64_t>(0, n_samples / d->n_points - d->n_taps + 1);
-    if (n_spec > 0x7fffffff) return fail(XCORR_ERR_UNSUPPORTED, "too many spectra");
+    *n_spec = std::max<int64_t>(0, n_samples / d->n_points - d->n_taps + 1);
+    if (*n_spec > 0x7fffffff) return fail(XCORR_ERR_UNSUPPORTED, "too many spectra");
+    return XCORR_OK;
+}
+
+}  // namespace
+
+xcorr_status xcorr_fstage_work_bytes(const xcorr_fstage_desc* d, int64_t n_samples, size_t* bytes)
+{
+    int64_t n_spec = 0;
+    xcorr_status s = check_fstage_desc(d, n_samples + (n_samples & 1), n_samples, &n_spec);
+    if (s != XCORR_OK) return s;
+    if (!bytes) return fail(XCORR_ERR_ARG, "null bytes");
+    *bytes = d->out_kind == XCORR_FSTAGE_CI4 ? (size_t)fstage_work_bytes(d->n_inputs, n_spec, d->chan_begin, d->n_chan)
+                                             : 0;
+    return XCORR_OK;
+}
+
+xcorr_status xcorr_fstage(const xcorr_fstage_desc* d, const void* d_adc, int64_t adc_stride, int64_t n_samples,
+                          const float* d_coeff, const float* d_gain, void* d_work, void* d_out, int64_t* n_spectra,
+                          void* stream)
+{
+    int64_t n_spec = 0;
+    xcorr_status s0 = check_fstage_desc(d, adc_stride, n_samples, &n_spec);
+    if (s0 != XCORR_OK) return s0;
     if (n_spectra) *n_spectra = n_spec;
     if (n_spec == 0) return XCORR_OK;
     xcorr_status s = check_ptr(d_adc, "d_adc");
     if (s == XCORR_OK) s = check_ptr(d_coeff, "d_coeff");
     if (s == XCORR_OK) s = check_ptr(d_gain, "d_gain");
     if (s == XCORR_OK) s = check_ptr(d_out, "d_out");
+    if (s == XCORR_OK && d->out_kind == XCORR_FSTAGE_CI4) s = check_ptr(d_work, "d_work");
     if (s != XCORR_OK) return s;
     FstageArgs a{};
     a.adc = (const int8_t*)d_adc;
@@ -606,6 +631,7 @@ xcorr_status xcorr_fstage(const xcorr_fstage_desc* d, const void* d_adc, int64_t
     a.coeff = d_coeff;
     a.gain = d_gain;
     a.out = d_out;
+    a.work = d_work;
     a.n_inputs = d->n_inputs;
     a.n_taps = d->n_taps;
     a.n_spectra = (int32_t)n_spec;

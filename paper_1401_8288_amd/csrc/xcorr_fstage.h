@@ -12,9 +12,13 @@ struct FstageArgs {
     const float* coeff;      // [n_taps][8192] prototype filter
     const float* gain;       // [n_inputs][n_chan]
     void* out;               // CI4: [n_chan][n_spectra][n_inputs] bytes; F32: [..][2] floats
+    void* work;              // CI4: [n_inputs][n_spectra][cp] bytes, input-major codes
     int32_t n_inputs, n_taps, n_spectra, chan_begin, n_chan, out_kind;
+    int32_t cp;              // channels per work row (set by the launcher)
 };
 
-hipError_t launch_fstage(const FstageArgs& a, hipStream_t s);
+// Bytes of the work buffer the CI4 output needs.
+int64_t fstage_work_bytes(int n_inputs, int64_t n_spectra, int chan_begin, int n_chan);
+hipError_t launch_fstage(FstageArgs a, hipStream_t s);
 
 }  // namespace xcorr

@@ -9,16 +9,18 @@
 // [-7, 7].  The real transform runs as one 4096-point complex transform of
 // z[n] = y[2n] + i y[2n+1] and a split into the even and odd halves.
 //
-// Work: a workgroup (256 threads) takes 16 inputs x a run of spectra and
+// Work: a workgroup (256 threads) takes one input and a run of spectra and
 // transforms them one after another.  The 4096-point transform is three
 // radix-16 passes (4096 = 16^3) with the data in registers (16 points per
-// thread) and two LDS exchanges between them; thread t keeps the filter
-// coefficients of the samples it loads in registers for the whole workgroup,
-// and the 4-bit results of its 16 channels for the 16 inputs in 64
-// registers, so every channel goes out as one 16-byte store of 16 inputs.
-// Twiddle factors are LDS tables built once per workgroup in double
-// precision.  fp32 arithmetic throughout; bound by VALU work (about 36
-// flops per sample against 1.5 bytes of HBM traffic).
+// thread) and LDS exchanges between them.  Thread t keeps the filter
+// coefficients of the samples it loads and the input's gains for its 16
+// channels in registers for the whole run, and the next spectrum's samples
+// load while the current one is transformed.  Its 16 channels' codes go out
+// as one 16-byte store, input-major; a second, HBM-bound kernel transposes
+// them into X-stage order.  Twiddle factors are LDS tables built once per
+// workgroup in double precision.  fp32 arithmetic throughout; bound by VALU
+// work (about 36 flops per sample against 2.5 bytes of HBM traffic, the
+// transpose included).
 #include "xcorr_fstage.h"
 
 namespace xcorr {
@@ -26,8 +28,7 @@ namespace {
 
 constexpr int kN = 8192;            // real transform length
 constexpr int kThreads = 256;
-constexpr int kG = 16;              // inputs per workgroup
-constexpr int kSpectra = 8;         // spectra per workgroup
+constexpr int kSpectra = 32;        // spectra per workgroup
 constexpr int kRow = 272;           // LDS row (float2) of a 16 x 256 pass layout
 constexpr int kBuf = 16 * kRow;     // 4352 float2
 
@@ -96,6 +97,28 @@ __device__ __forceinline__ uint32_t nibble_pair(float re, float im)
     return ((uint32_t)(qr & 0xF) << 4) | (uint32_t)(qi & 0xF);
 }
 
+// LDS writes visible, then a workgroup barrier; global loads stay in flight
+// (__syncthreads would also wait for them)
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// raw 16-bit pairs (samples 2n, 2n + 1, n = 256 n2 + t) of the P frames of spectrum m
+template <int P>
+__device__ __forceinline__ void load_frames(uint32_t (&xr)[P][16], const uint16_t* x, int t)
+{
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2) xr[p][n2] = x[p * (kN / 2) + 256 * n2 + t];
+}
+
+// One workgroup: one input, spectra m0 .. m0 + kSpectra - 1.
+// OUT 0: 4-bit codes in input-major order, work[a][m][cp] with channel
+//        k at cp = k - base (base = chan_begin rounded down to 16), one
+//        16-byte store per thread (channels outside the selection get 0);
+// OUT 1: equalised values, float2 out[c][m][a].
 template <int P, int OUT>
 __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
 {
@@ -105,11 +128,15 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
     __shared__ float2 TB[16];           // W8192^j
 
     const int t = threadIdx.x;
-    const int n_groups = (a.n_inputs + kG - 1) / kG;
-    const int g = blockIdx.x % n_groups;
-    const int m0 = (blockIdx.x / n_groups) * kSpectra;
-    const int a0 = g * kG;
+    const int ai = blockIdx.x % a.n_inputs;
+    const int m0 = (blockIdx.x / a.n_inputs) * kSpectra;
     const int m1 = min(m0 + kSpectra, a.n_spectra);
+    const int k_first = 16 * t;                  // this thread's channels k_first .. k_first + 15
+    const int base = a.chan_begin & ~15;
+
+    const uint16_t* xa = (const uint16_t*)(a.adc + ai * a.adc_stride);
+    uint32_t xr[P][16];
+    load_frames<P>(xr, xa + (int64_t)m0 * (kN / 2), t);
 
 #pragma unroll
     for (int k0 = 0; k0 < 16; ++k0) T1[k0 * 256 + t] = twiddle((t * k0) & 4095, 4096);
@@ -117,140 +144,164 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
     if (t < 16) TB[t] = twiddle(t, kN);
     const float2 ta = twiddle(16 * t, kN);       // W8192^(16 t)
 
-    // prototype-filter coefficients of the samples this thread loads,
-    // h[p N + 512 n2 + 2 t + e]; re-read (from cache) for every transform
-    const float2* hc = (const float2*)(a.coeff + 2 * t);
-
-    const int k_first = 16 * t;                  // this thread's channels k_first .. k_first + 15
-    const bool full = a0 + kG <= a.n_inputs && (a.n_inputs % 16) == 0;
+    // prototype-filter coefficients of this thread's samples,
+    // h[p N + 512 n2 + 2 t + e], and the input's gains for its channels
+    float2 h[P][16];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2) h[p][n2] = *(const float2*)(a.coeff + p * kN + 512 * n2 + 2 * t);
+    float gn[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int c = k_first + j - a.chan_begin;
+        gn[j] = (c >= 0 && c < a.n_chan) ? a.gain[(int64_t)ai * a.n_chan + c] : 0.0f;
+    }
+    const bool writes = k_first + 16 > a.chan_begin && k_first < a.chan_begin + a.n_chan;
     __syncthreads();
 
     for (int m = m0; m < m1; ++m) {
-        uint32_t st[16][4];                      // 4-bit results: channel j, inputs 4 w .. 4 w + 3
+        // ---- filter bank: z[256 n2 + t] = y[2n] + i y[2n + 1]
+        float2 v[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
+        for (int n2 = 0; n2 < 16; ++n2) {
+            float re = 0.f, im = 0.f;
 #pragma unroll
-            for (int w = 0; w < 4; ++w) st[j][w] = 0;
-
-        for (int s = 0; s < kG; ++s) {
-            const int ai = a0 + s;
-            uint32_t q[16];
-            if (ai < a.n_inputs) {
-                // ---- filter bank: z[256 n2 + t] = y[2n] + i y[2n + 1]
-                const uint16_t* x = (const uint16_t*)(a.adc + ai * a.adc_stride + (int64_t)m * kN);
-                // an opaque zero keeps the coefficient loads inside the loop
-                // (held in registers for the whole workgroup they would not
-                // leave room for the 4-bit results)
-                int zero;
-                asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
-                const float2* hz = hc + zero;
-                float2 v[16];
-#pragma unroll
-                for (int n2 = 0; n2 < 16; ++n2) {
-                    float re = 0.f, im = 0.f;
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const uint32_t u = x[p * (kN / 2) + 256 * n2 + t];
-                        const float2 hh = hz[p * (kN / 2) + 256 * n2];
-                        re = fmaf(hh.x, (float)(int8_t)(u & 0xFF), re);
-                        im = fmaf(hh.y, (float)(int8_t)(u >> 8), im);
-                    }
-                    v[n2] = make_float2(re, im);
-                    // bound the loads in flight (and their registers)
-                    if ((n2 & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-                }
-                // ---- pass 1 over n2 (thread t = n_lo), twiddle W4096^(n_lo k0)
-                dft16(v);
-                __syncthreads();                 // previous transform's reads of L are done
-#pragma unroll
-                for (int k0 = 0; k0 < 16; ++k0) {
-                    const float2 y = v[slot_of(k0)];
-                    L[k0 * kRow + t] = k0 ? cmul(y, T1[k0 * 256 + t]) : y;
-                }
-                __syncthreads();
-                // ---- pass 2 over n1 (thread = (k0, n0)), twiddle W256^(n0 k1)
-                {
-                    const int k0 = t >> 4, n0 = t & 15;
-#pragma unroll
-                    for (int n1 = 0; n1 < 16; ++n1) v[n1] = L[k0 * kRow + 16 * n1 + n0];
-                    dft16(v);
-                    __syncthreads();
-#pragma unroll
-                    for (int k1 = 0; k1 < 16; ++k1) {
-                        const float2 y = v[slot_of(k1)];
-                        L[k0 * kRow + 17 * k1 + n0] = k1 ? cmul(y, T2[k1 * 16 + n0]) : y;
-                    }
-                }
-                __syncthreads();
-                // ---- pass 3 over n0 (thread = (k0, k1)): Z[k0 + 16 k1 + 256 k2]
-                {
-                    const int k0 = t >> 4, k1 = t & 15;
-#pragma unroll
-                    for (int n0 = 0; n0 < 16; ++n0) v[n0] = L[k0 * kRow + 17 * k1 + n0];
-                    dft16(v);
-                    __syncthreads();
-#pragma unroll
-                    for (int k2 = 0; k2 < 16; ++k2) {
-                        const int k = k0 + 16 * k1 + 256 * k2;
-                        L[k + (k >> 4)] = v[slot_of(k2)];
-                    }
-                }
-                __syncthreads();
-                // ---- real split, equalise, requantise this thread's channels
-#pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const int k = k_first + j;
-                    const int kk = (4096 - k) & 4095;
-                    const float2 zk = L[k + (k >> 4)];
-                    const float2 zc = L[kk + (kk >> 4)];
-                    // E = (Z[k] + conj Z[-k]) / 2, O = -i (Z[k] - conj Z[-k]) / 2
-                    const float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
-                    const float2 o = make_float2(0.5f * (zk.y + zc.y), -0.5f * (zk.x - zc.x));
-                    const float2 X = cadd(e, cmul(o, cmul(ta, TB[j])));
-                    const int c = k - a.chan_begin;
-                    q[j] = 0;
-                    if (c >= 0 && c < a.n_chan) {
-                        const float gn = a.gain[(int64_t)ai * a.n_chan + c];
-                        if constexpr (OUT == 0) {
-                            q[j] = nibble_pair(gn * X.x, gn * X.y);
-                        } else {
-                            float2* o32 = (float2*)a.out;
-                            o32[((int64_t)c * a.n_spectra + m) * a.n_inputs + ai] = make_float2(gn * X.x, gn * X.y);
-                        }
-                    }
-                    if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < 16; ++j) q[j] = 0;
+            for (int p = 0; p < P; ++p) {
+                re = fmaf(h[p][n2].x, (float)(int8_t)(xr[p][n2] & 0xFF), re);
+                im = fmaf(h[p][n2].y, (float)(int8_t)(xr[p][n2] >> 8), im);
             }
-            if constexpr (OUT == 0) {
-                // shift input s's byte in at the top: after 16 inputs input s
-                // sits in byte s % 4 of word s / 4
+            v[n2] = make_float2(re, im);
+        }
+        // the next spectrum's samples load while this one is transformed
+        if (m + 1 < m1) load_frames<P>(xr, xa + (int64_t)(m + 1) * (kN / 2), t);
+
+        // ---- pass 1 over n2 (thread t = n_lo), twiddle W4096^(n_lo k0)
+        dft16(v);
+        lds_barrier();                           // previous transform's reads of L are done
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    st[j][0] = __builtin_amdgcn_alignbit(st[j][1], st[j][0], 8);
-                    st[j][1] = __builtin_amdgcn_alignbit(st[j][2], st[j][1], 8);
-                    st[j][2] = __builtin_amdgcn_alignbit(st[j][3], st[j][2], 8);
-                    st[j][3] = __builtin_amdgcn_alignbit(q[j], st[j][3], 8);
-                }
+        for (int k0 = 0; k0 < 16; ++k0) {
+            const float2 y = v[slot_of(k0)];
+            L[k0 * kRow + t] = k0 ? cmul(y, T1[k0 * 256 + t]) : y;
+        }
+        lds_barrier();
+        // ---- pass 2 over n1 (thread = (k0, n0)), twiddle W256^(n0 k1)
+        {
+            const int k0 = t >> 4, n0 = t & 15;
+#pragma unroll
+            for (int n1 = 0; n1 < 16; ++n1) v[n1] = L[k0 * kRow + 16 * n1 + n0];
+            dft16(v);
+            lds_barrier();
+#pragma unroll
+            for (int k1 = 0; k1 < 16; ++k1) {
+                const float2 y = v[slot_of(k1)];
+                L[k0 * kRow + 17 * k1 + n0] = k1 ? cmul(y, T2[k1 * 16 + n0]) : y;
             }
         }
-        if constexpr (OUT == 0) {
-            uint8_t* o8 = (uint8_t*)a.out;
+        lds_barrier();
+        // ---- pass 3 over n0 (thread = (k0, k1)): Z[k0 + 16 k1 + 256 k2]
+        {
+            const int k0 = t >> 4, k1 = t & 15;
+#pragma unroll
+            for (int n0 = 0; n0 < 16; ++n0) v[n0] = L[k0 * kRow + 17 * k1 + n0];
+            dft16(v);
+            lds_barrier();
+#pragma unroll
+            for (int k2 = 0; k2 < 16; ++k2) {
+                const int k = k0 + 16 * k1 + 256 * k2;
+                L[k + (k >> 4)] = v[slot_of(k2)];
+            }
+        }
+        lds_barrier();
+        // ---- real split, equalise, requantise this thread's channels
+        if (writes) {
+            uint32_t q[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                const int c = k_first + j - a.chan_begin;
-                if (c < 0 || c >= a.n_chan) continue;
-                uint8_t* dst = o8 + ((int64_t)c * a.n_spectra + m) * a.n_inputs + a0;
-                if (full) {
-                    *(uint4*)dst = make_uint4(st[j][0], st[j][1], st[j][2], st[j][3]);
+                const int k = k_first + j;
+                const int kk = (4096 - k) & 4095;
+                const float2 zk = L[k + (k >> 4)];
+                const float2 zc = L[kk + (kk >> 4)];
+                // E = (Z[k] + conj Z[-k]) / 2, O = -i (Z[k] - conj Z[-k]) / 2
+                const float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
+                const float2 o = make_float2(0.5f * (zk.y + zc.y), -0.5f * (zk.x - zc.x));
+                const float2 X = cadd(e, cmul(o, cmul(ta, TB[j])));
+                if constexpr (OUT == 0) {
+                    q[j >> 2] |= nibble_pair(gn[j] * X.x, gn[j] * X.y) << (8 * (j & 3));
                 } else {
-#pragma unroll
-                    for (int s = 0; s < kG; ++s)   // constant indices keep st in registers
-                        if (a0 + s < a.n_inputs) dst[s] = (uint8_t)(st[j][s >> 2] >> (8 * (s & 3)));
+                    const int c = k - a.chan_begin;
+                    if (c >= 0 && c < a.n_chan)
+                        ((float2*)a.out)[((int64_t)c * a.n_spectra + m) * a.n_inputs + ai] =
+                            make_float2(gn[j] * X.x, gn[j] * X.y);
                 }
             }
+            if constexpr (OUT == 0)
+                *(uint4*)((uint8_t*)a.work + ((int64_t)ai * a.n_spectra + m) * a.cp + (k_first - base)) =
+                    make_uint4(q[0], q[1], q[2], q[3]);
+        }
+    }
+}
+
+// work[a][m][cp] -> out[c][m][a] (c = cp - (chan_begin - base)), bytes.  A
+// workgroup moves a 128-input x 128-channel tile of one spectrum: dword
+// loads along channels, 4 x 4 byte transposes in registers, an LDS tile of
+// [input / 4][channel] dwords, and 16-byte stores along inputs.
+__global__ void __launch_bounds__(kThreads) fstage_transpose_kernel(FstageArgs a)
+{
+    __shared__ uint32_t T[32][128 + 4];
+    const int t = threadIdx.x;
+    const int n_ct = (a.cp + 127) / 128, n_at = (a.n_inputs + 127) / 128;
+    int b = blockIdx.x;
+    const int ct = b % n_ct;  b /= n_ct;
+    const int at = b % n_at;
+    const int m = b / n_at;
+    const int cp0 = ct * 128, a0 = at * 128;
+    const int off = a.chan_begin - (a.chan_begin & ~15);
+    const uint8_t* w = (const uint8_t*)a.work;
+
+    {
+        const int c4 = t & 31, aq = t >> 5;      // channels cp0 + 4 c4 .. + 3, inputs a0 + 16 aq ..
+        const int cp = cp0 + 4 * c4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t r[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int ar = a0 + 16 * aq + 4 * i + k;
+                r[k] = (ar < a.n_inputs && cp < a.cp)
+                           ? *(const uint32_t*)(w + ((int64_t)ar * a.n_spectra + m) * a.cp + cp) : 0u;
+            }
+            // 4 x 4 byte transpose: column cc = (r0[cc], r1[cc], r2[cc], r3[cc])
+            const uint32_t t0 = __builtin_amdgcn_perm(r[1], r[0], 0x05010400u);
+            const uint32_t t1 = __builtin_amdgcn_perm(r[1], r[0], 0x07030602u);
+            const uint32_t t2 = __builtin_amdgcn_perm(r[3], r[2], 0x05010400u);
+            const uint32_t t3 = __builtin_amdgcn_perm(r[3], r[2], 0x07030602u);
+            uint4 col;
+            col.x = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+            col.y = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+            col.z = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+            col.w = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+            *(uint4*)&T[4 * aq + i][4 * c4] = col;
+        }
+    }
+    __syncthreads();
+    {
+        const int cl = t & 127, half = t >> 7;
+        const int c = cp0 + cl - off;            // output channel
+        if (c < 0 || c >= a.n_chan || cp0 + cl >= a.cp) return;
+        uint32_t d[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) d[q] = T[16 * half + q][cl];
+        const int ab = a0 + 64 * half;
+        uint8_t* o = (uint8_t*)a.out + ((int64_t)c * a.n_spectra + m) * a.n_inputs + ab;
+        if (ab + 64 <= a.n_inputs && (a.n_inputs & 15) == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                ((uint4*)o)[q] = make_uint4(d[4 * q], d[4 * q + 1], d[4 * q + 2], d[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 64; ++q)
+                if (ab + q < a.n_inputs) o[q] = (uint8_t)(d[q >> 2] >> (8 * (q & 3)));
         }
     }
 }
@@ -265,14 +316,25 @@ hipError_t launch_p(const FstageArgs& a, dim3 grid, hipStream_t s)
 
 }  // namespace
 
-hipError_t launch_fstage(const FstageArgs& a, hipStream_t s)
+int64_t fstage_work_bytes(int n_inputs, int64_t n_spectra, int chan_begin, int n_chan)
+{
+    const int64_t base = chan_begin & ~15;
+    const int64_t cp = (chan_begin + n_chan + 15) / 16 * 16 - base;
+    return (int64_t)n_inputs * n_spectra * cp;
+}
+
+hipError_t launch_fstage(FstageArgs a, hipStream_t s)
 {
     if (a.n_spectra <= 0) return hipSuccess;
-    const int64_t n_groups = (a.n_inputs + kG - 1) / kG;
-    const int64_t blocks = n_groups * ((a.n_spectra + kSpectra - 1) / kSpectra);
+    a.cp = (int32_t)((a.chan_begin + a.n_chan + 15) / 16 * 16 - (a.chan_begin & ~15));
+    const int64_t blocks = (int64_t)a.n_inputs * ((a.n_spectra + kSpectra - 1) / kSpectra);
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)blocks);
-    return a.n_taps == 1 ? launch_p<1>(a, grid, s) : launch_p<2>(a, grid, s);
+    hipError_t e = a.n_taps == 1 ? launch_p<1>(a, dim3((unsigned)blocks), s) : launch_p<2>(a, dim3((unsigned)blocks), s);
+    if (e != hipSuccess || a.out_kind != 0) return e;
+    const int64_t tiles = (int64_t)((a.cp + 127) / 128) * ((a.n_inputs + 127) / 128) * a.n_spectra;
+    if (tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(fstage_transpose_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace xcorr

@@ -34,7 +34,8 @@ EXPORTS = ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dum
            "xcorr_graph_launch", "xcorr_graph_destroy", "xcorr_batch_destroy",
            "xcorr_server_create", "xcorr_server_open", "xcorr_server_submit", "xcorr_server_poll",
            "xcorr_server_wait", "xcorr_server_close", "xcorr_server_query", "xcorr_server_destroy",
-           "xcorr_corner_turn", "xcorr_dump_tiles", "xcorr_accumulate_gated", "xcorr_fstage")
+           "xcorr_corner_turn", "xcorr_dump_tiles", "xcorr_accumulate_gated", "xcorr_fstage",
+           "xcorr_fstage_work_bytes")
 
 
 class PlanDesc(ctypes.Structure):
@@ -138,7 +139,8 @@ def _load():
     L.xcorr_corner_turn.argtypes = [vp, vp, P(PacketLayout), i32, vp, vp]
     L.xcorr_dump_tiles.argtypes = [vp, vp, vp, i32, P(DumpInfo)]
     L.xcorr_accumulate_gated.argtypes = [P(vp), i32, vp, i64, vp]
-    L.xcorr_fstage.argtypes = [P(FstageDesc), vp, i64, i64, vp, vp, vp, P(i64), vp]
+    L.xcorr_fstage.argtypes = [P(FstageDesc), vp, i64, i64, vp, vp, vp, vp, P(i64), vp]
+    L.xcorr_fstage_work_bytes.argtypes = [P(FstageDesc), i64, P(ctypes.c_size_t)]
     for name in EXPORTS:
         if name not in ("xcorr_strerror", "xcorr_last_error", "xcorr_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -557,11 +559,13 @@ def accumulate_gated(plans, x: torch.Tensor, gate) -> None:
 
 def fstage(adc: torch.Tensor, coeff: torch.Tensor, gain: torch.Tensor, chan_begin: int, n_chan: int,
            n_taps: int = 2, n_points: int = 8192, out_kind: str = "ci4", n_samples: int | None = None,
-           out: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+           out: torch.Tensor | None = None, work: torch.Tensor | None = None,
+           stream: torch.cuda.Stream | None = None) -> torch.Tensor:
     """F-stage: int8 ADC samples [n_inputs][stride] -> X-stage input (see xcorr_fstage).
 
     Returns uint8 [n_chan][n_spectra][n_inputs] ("ci4") or float32
-    [n_chan][n_spectra][n_inputs][2] ("f32")."""
+    [n_chan][n_spectra][n_inputs][2] ("f32").  `work` (uint8, device) is the
+    scratch of the CI4 output; one of the needed size is made if absent."""
     if adc.dtype != torch.int8 or adc.dim() != 2 or adc.stride(1) != 1 or not adc.is_cuda:
         raise ValueError("adc must be an int8 device tensor [n_inputs][samples] with unit sample stride")
     n_in = adc.shape[0]
@@ -580,10 +584,15 @@ def fstage(adc: torch.Tensor, coeff: torch.Tensor, gain: torch.Tensor, chan_begi
     elif tuple(out.shape) != shape or out.dtype != dt or not out.is_contiguous():
         raise ValueError("output must be a contiguous %s tensor %s" % (dt, shape))
     d = FstageDesc(n_in, n_points, n_taps, chan_begin, n_chan, kind)
+    nb = ctypes.c_size_t(0)
+    _check(lib.xcorr_fstage_work_bytes(ctypes.byref(d), n_samples, ctypes.byref(nb)))
+    if work is None or work.numel() < nb.value:
+        work = torch.empty(max(1, nb.value), dtype=torch.uint8, device=adc.device) if nb.value else None
     got = ctypes.c_int64(-1)
     s = stream if stream is not None else torch.cuda.current_stream()
     _check(lib.xcorr_fstage(ctypes.byref(d), ctypes.c_void_p(adc.data_ptr()), adc.stride(0), n_samples,
                             ctypes.c_void_p(coeff.data_ptr()), ctypes.c_void_p(gain.data_ptr()),
+                            ctypes.c_void_p(work.data_ptr() if work is not None else 0),
                             ctypes.c_void_p(out.data_ptr() if out.numel() else 0), ctypes.byref(got),
                             ctypes.c_void_p(int(s.cuda_stream))))
     if got.value != n_spec:

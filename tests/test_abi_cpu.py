@@ -185,7 +185,7 @@ def test_fstage_argument_checks():
 
     def call(d, stride=16384, n_samples=16384):
         return L.xcorr_fstage(ctypes.byref(d) if d is not None else None, None, stride, n_samples,
-                              None, None, None, ctypes.byref(n), None)
+                              None, None, None, None, ctypes.byref(n), None)
 
     ok = dict(n_inputs=4, n_points=8192, n_taps=2, chan_begin=0, n_chan=16, out_kind=0)
     assert call(None) == -1
@@ -200,3 +200,9 @@ def test_fstage_argument_checks():
     assert call(xcorr.FstageDesc(**ok), n_samples=16383) == 0 and n.value == 0
     # a full spectrum needs the device buffers
     assert call(xcorr.FstageDesc(**ok)) == -1 and n.value == 1
+    nb = ctypes.c_size_t(0)
+    assert L.xcorr_fstage_work_bytes(ctypes.byref(xcorr.FstageDesc(**dict(ok, chan_begin=5, n_chan=20))),
+                                     3 * 8192, ctypes.byref(nb)) == 0
+    assert nb.value == 4 * 2 * 32                     # channels 5..24 -> rows of 0..31
+    assert L.xcorr_fstage_work_bytes(ctypes.byref(xcorr.FstageDesc(**dict(ok, out_kind=1))),
+                                     3 * 8192, ctypes.byref(nb)) == 0 and nb.value == 0
