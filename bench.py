@@ -218,6 +218,51 @@ def corner_turn_leg(torch, xcorr, w, reps=5, n_fengines=16, spectra_per_packet=8
             "hbm_frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 4)}
 
 
+def fstage_leg(torch, xcorr, w, reps=3, n_taps=2):
+    """The GPU F-stage that makes the workload's input: w.n_inputs int8 ADC
+    streams through the 2-tap 8192-point PFB, all 4096 channels, w.n_time
+    spectra, requantised to 4+4 bits in X-stage order (transform kernel plus
+    transpose).  Algorithmic work per ADC sample: 2 P flops of filter bank and
+    2.5 log2(N) of real transform; HBM bytes: the samples once, the codes
+    written, read and written again by the transpose."""
+    from paper_1401_8288_amd import synth
+    N = 8192
+    if w.n_channels != N // 2:
+        return None
+    dev = torch.device("cuda:0")
+    n_samples = (w.n_time + n_taps - 1) * N
+    adc = synth.adc_input(w.n_inputs, n_samples, 1, device=dev)
+    h = synth.pfb_coefficients(n_taps, N).to(dev)
+    gain = synth.fstage_gains(w.n_inputs, w.n_channels, h).to(dev)
+    out = torch.empty((w.n_channels, w.n_time, w.n_inputs), dtype=torch.uint8, device=dev)
+    work = torch.empty(w.n_inputs * w.n_time * w.n_channels, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    run = lambda: xcorr.fstage(adc, h, gain, 0, w.n_channels, n_taps=n_taps, out=out, work=work, stream=stream)
+    run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    samples = w.n_inputs * w.n_time * N
+    flops = samples * (2 * n_taps + 2.5 * 13)
+    codes = w.n_inputs * w.n_time * w.n_channels
+    nbytes = w.n_inputs * n_samples + 3 * codes
+    del adc, out, work
+    torch.cuda.empty_cache()
+    return {"config": "%d inputs, %d-tap %d-point PFB, %d channels, %d spectra, CI4 out in X-stage order"
+                      % (w.n_inputs, n_taps, N, w.n_channels, w.n_time),
+            "ms": round(ms, 4), "gsamples_s": round(samples / ms / 1e6, 1),
+            "bound": "alu", "achieved": round(flops / ms / 1e9, 2), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(flops / ms / 1e9 / PEAK_FP32_TFLOPS, 4),
+            "algorithmic_flops_per_sample": 2 * n_taps + 2.5 * 13,
+            "hbm_bytes": nbytes, "hbm_gbs": round(nbytes / ms / 1e6, 1)}
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The oracle on a bounded sample of the same workload (host cores)."""
     import oracle
@@ -248,6 +293,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-compare", action="store_true", help="skip the fp16 / fp32 kernels")
     ap.add_argument("--no-corner-turn", action="store_true", help="skip the corner-turn leg")
+    ap.add_argument("--no-fstage", action="store_true", help="skip the F-stage leg")
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="length of the batched-streaming leg (0 skips it)")
     ap.add_argument("--serving-speedup", type=float, default=40.0,
@@ -330,6 +376,11 @@ def main():
         log("corner turn at the same size")
         result["corner_turn"] = corner_turn_leg(torch, xcorr, w)
         log("corner turn:", result["corner_turn"])
+
+    if not args.no_fstage:
+        log("F-stage making the same workload")
+        result["fstage"] = fstage_leg(torch, xcorr, w)
+        log("F-stage:", result["fstage"])
 
     if args.serving_seconds > 0:
         log("batched streaming leg: %.1f s at %.0fx real time" % (args.serving_seconds, args.serving_speedup))

@@ -90,13 +90,6 @@ __device__ __forceinline__ float2 twiddle(int r, int n)
     return make_float2((float)c, (float)-s);
 }
 
-__device__ __forceinline__ uint32_t nibble_pair(float re, float im)
-{
-    const int qr = (int)fminf(fmaxf(__builtin_rintf(re), -7.0f), 7.0f);
-    const int qi = (int)fminf(fmaxf(__builtin_rintf(im), -7.0f), 7.0f);
-    return ((uint32_t)(qr & 0xF) << 4) | (uint32_t)(qi & 0xF);
-}
-
 // LDS writes visible, then a workgroup barrier; global loads stay in flight
 // (__syncthreads would also wait for them)
 __device__ __forceinline__ void lds_barrier()
@@ -151,11 +144,11 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
     for (int p = 0; p < P; ++p)
 #pragma unroll
         for (int n2 = 0; n2 < 16; ++n2) h[p][n2] = *(const float2*)(a.coeff + p * kN + 512 * n2 + 2 * t);
-    float gn[16];
+    float gh[16];                                // gain / 2 (the split's 1/2 folded in)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int c = k_first + j - a.chan_begin;
-        gn[j] = (c >= 0 && c < a.n_chan) ? a.gain[(int64_t)ai * a.n_chan + c] : 0.0f;
+        gh[j] = (c >= 0 && c < a.n_chan) ? 0.5f * a.gain[(int64_t)ai * a.n_chan + c] : 0.0f;
     }
     const bool writes = k_first + 16 > a.chan_begin && k_first < a.chan_begin + a.n_chan;
     __syncthreads();
@@ -222,17 +215,23 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
                 const int kk = (4096 - k) & 4095;
                 const float2 zk = L[k + (k >> 4)];
                 const float2 zc = L[kk + (kk >> 4)];
-                // E = (Z[k] + conj Z[-k]) / 2, O = -i (Z[k] - conj Z[-k]) / 2
-                const float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
-                const float2 o = make_float2(0.5f * (zk.y + zc.y), -0.5f * (zk.x - zc.x));
-                const float2 X = cadd(e, cmul(o, cmul(ta, TB[j])));
+                // X = (s - i W8192^k d) / 2 with s = Z[k] + conj Z[-k] and
+                // d = Z[k] - conj Z[-k] (the even- and odd-sample transforms)
+                const float sx = zk.x + zc.x, sy = zk.y - zc.y, dx = zk.x - zc.x, dy = zk.y + zc.y;
+                const float2 w = cmul(ta, TB[j]);
+                const float vr = gh[j] * fmaf(w.x, dy, fmaf(w.y, dx, sx));
+                const float vi = gh[j] * fmaf(-w.x, dx, fmaf(w.y, dy, sy));
                 if constexpr (OUT == 0) {
-                    q[j >> 2] |= nibble_pair(gn[j] * X.x, gn[j] * X.y) << (8 * (j & 3));
+                    // clamp to [-7, 7], then round half to even by adding
+                    // 1.5 * 2^23: the integer is left in the low mantissa
+                    // bits, two's complement
+                    const uint32_t br = __float_as_uint(__builtin_amdgcn_fmed3f(vr, -7.0f, 7.0f) + 12582912.0f);
+                    const uint32_t bi = __float_as_uint(__builtin_amdgcn_fmed3f(vi, -7.0f, 7.0f) + 12582912.0f);
+                    q[j >> 2] |= (((br & 0xFu) << 4) | (bi & 0xFu)) << (8 * (j & 3));
                 } else {
                     const int c = k - a.chan_begin;
                     if (c >= 0 && c < a.n_chan)
-                        ((float2*)a.out)[((int64_t)c * a.n_spectra + m) * a.n_inputs + ai] =
-                            make_float2(gn[j] * X.x, gn[j] * X.y);
+                        ((float2*)a.out)[((int64_t)c * a.n_spectra + m) * a.n_inputs + ai] = make_float2(vr, vi);
                 }
             }
             if constexpr (OUT == 0)

@@ -189,3 +189,29 @@ def test_tone_lands_in_its_channel():
     torch.cuda.synchronize()
     p = (out.double() ** 2).sum(dim=-1).mean(dim=(1, 2))
     assert int(torch.argmax(p)) == k0
+
+
+def test_full_size_sampled_against_the_oracle():
+    # the benchmark's configuration and launch: 512 inputs, 2-tap 8192-point
+    # PFB, all 4096 channels, 4096 spectra (17 GB of samples); sampled
+    # (input, spectrum) pairs, every channel, against the oracle
+    X = xc()
+    n_in, n_spec, P = 512, 4096, 2
+    say("fstage full size", n_in, n_spec)
+    adc = synth.adc_input(n_in, (n_spec + P - 1) * N, 1, device=DEV)
+    h = synth.pfb_coefficients(P, N)
+    gain = synth.fstage_gains(n_in, N // 2, h)
+    out = X.fstage(adc, h.to(DEV), gain.to(DEV), 0, N // 2)
+    torch.cuda.synchronize()
+    hd, gd = h.numpy().astype(np.float64), gain.numpy().astype(np.float64)
+    rng = np.random.default_rng(0)
+    picks = [(0, 0), (n_in - 1, n_spec - 1), (255, 2048)] + \
+        [(int(a), int(m)) for a, m in zip(rng.integers(0, n_in, 21), rng.integers(0, n_spec, 21))]
+    for a, m in picks:
+        seg = adc[a:a + 1, m * N:(m + P) * N].cpu().numpy()
+        v = oracle.fstage(seg, hd, gd[a:a + 1], N, P, 0, N // 2, out="c128")
+        got = out[:, m, a].cpu().numpy()[:, None, None]
+        ok, _ = check_codes(got, v, frame_bound(seg, h, P, float(np.abs(gd[a]).max())))
+        assert ok.all(), (a, m)
+    del adc, out
+    torch.cuda.empty_cache()
