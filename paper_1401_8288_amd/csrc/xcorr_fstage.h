@@ -12,7 +12,7 @@ struct FstageArgs {
     const float* coeff;      // [n_taps][8192] prototype filter
     const float* gain;       // [n_inputs][n_chan]
     void* out;               // CI4: [n_chan][n_spectra][n_inputs] bytes; F32: [..][2] floats
-    void* work;              // CI4: [n_inputs][n_spectra][cp] bytes, input-major codes
+    void* work;              // CI4: [n_spectra][n_inputs][cp] bytes, channel-fastest codes
     int32_t n_inputs, n_taps, n_spectra, chan_begin, n_chan, out_kind;
     int32_t cp;              // channels per work row (set by the launcher)
 };

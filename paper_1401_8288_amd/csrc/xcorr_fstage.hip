@@ -108,7 +108,7 @@ __device__ __forceinline__ void load_frames(uint32_t (&xr)[P][16], const uint16_
 }
 
 // One workgroup: one input, spectra m0 .. m0 + kSpectra - 1.
-// OUT 0: 4-bit codes in input-major order, work[a][m][cp] with channel
+// OUT 0: 4-bit codes in input-major order, work[m][a][cp] with channel
 //        k at cp = k - base (base = chan_begin rounded down to 16), one
 //        16-byte store per thread (channels outside the selection get 0);
 // OUT 1: equalised values, float2 out[c][m][a].
@@ -235,25 +235,28 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
                 }
             }
             if constexpr (OUT == 0)
-                *(uint4*)((uint8_t*)a.work + ((int64_t)ai * a.n_spectra + m) * a.cp + (k_first - base)) =
+                *(uint4*)((uint8_t*)a.work + ((int64_t)m * a.n_inputs + ai) * a.cp + (k_first - base)) =
                     make_uint4(q[0], q[1], q[2], q[3]);
         }
     }
 }
 
-// work[a][m][cp] -> out[c][m][a] (c = cp - (chan_begin - base)), bytes.  A
+// work[m][a][cp] -> out[c][m][a] (c = cp - (chan_begin - base)), bytes.  A
 // workgroup moves a 128-input x 128-channel tile of one spectrum: dword
 // loads along channels, 4 x 4 byte transposes in registers, an LDS tile of
-// [input / 4][channel] dwords, and 16-byte stores along inputs.
+// [input / 4][channel] dwords, and 16-byte stores along inputs, eight lanes
+// to a 128-byte output row.
 __global__ void __launch_bounds__(kThreads) fstage_transpose_kernel(FstageArgs a)
 {
     __shared__ uint32_t T[32][128 + 4];
     const int t = threadIdx.x;
     const int n_ct = (a.cp + 127) / 128, n_at = (a.n_inputs + 127) / 128;
+    // spectra vary fastest over the grid: workgroups running together touch
+    // neighbouring rows of both buffers (few pages)
     int b = blockIdx.x;
-    const int ct = b % n_ct;  b /= n_ct;
-    const int at = b % n_at;
-    const int m = b / n_at;
+    const int m = b % a.n_spectra;  b /= a.n_spectra;
+    const int ct = b % n_ct;
+    const int at = b / n_ct;
     const int cp0 = ct * 128, a0 = at * 128;
     const int off = a.chan_begin - (a.chan_begin & ~15);
     const uint8_t* w = (const uint8_t*)a.work;
@@ -268,7 +271,7 @@ __global__ void __launch_bounds__(kThreads) fstage_transpose_kernel(FstageArgs a
             for (int k = 0; k < 4; ++k) {
                 const int ar = a0 + 16 * aq + 4 * i + k;
                 r[k] = (ar < a.n_inputs && cp < a.cp)
-                           ? *(const uint32_t*)(w + ((int64_t)ar * a.n_spectra + m) * a.cp + cp) : 0u;
+                           ? *(const uint32_t*)(w + ((int64_t)m * a.n_inputs + ar) * a.cp + cp) : 0u;
             }
             // 4 x 4 byte transpose: column cc = (r0[cc], r1[cc], r2[cc], r3[cc])
             const uint32_t t0 = __builtin_amdgcn_perm(r[1], r[0], 0x05010400u);
@@ -285,22 +288,24 @@ __global__ void __launch_bounds__(kThreads) fstage_transpose_kernel(FstageArgs a
     }
     __syncthreads();
     {
-        const int cl = t & 127, half = t >> 7;
-        const int c = cp0 + cl - off;            // output channel
-        if (c < 0 || c >= a.n_chan || cp0 + cl >= a.cp) return;
-        uint32_t d[16];
+        // eight lanes write one channel's 128 inputs: full 128-byte rows
+        const int q = t & 7;                     // inputs a0 + 16 q .. + 15
+        const int ab = a0 + 16 * q;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) d[q] = T[16 * half + q][cl];
-        const int ab = a0 + 64 * half;
-        uint8_t* o = (uint8_t*)a.out + ((int64_t)c * a.n_spectra + m) * a.n_inputs + ab;
-        if (ab + 64 <= a.n_inputs && (a.n_inputs & 15) == 0) {
+        for (int pass = 0; pass < 4; ++pass) {
+            const int cl = 32 * pass + (t >> 3);
+            const int c = cp0 + cl - off;        // output channel
+            if (c < 0 || c >= a.n_chan || cp0 + cl >= a.cp || ab >= a.n_inputs) continue;
+            const uint4 d = make_uint4(T[4 * q][cl], T[4 * q + 1][cl], T[4 * q + 2][cl], T[4 * q + 3][cl]);
+            uint8_t* o = (uint8_t*)a.out + ((int64_t)c * a.n_spectra + m) * a.n_inputs + ab;
+            if (ab + 16 <= a.n_inputs && (a.n_inputs & 15) == 0) {
+                *(uint4*)o = d;
+            } else {
+                const uint32_t dw[4] = {d.x, d.y, d.z, d.w};
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                ((uint4*)o)[q] = make_uint4(d[4 * q], d[4 * q + 1], d[4 * q + 2], d[4 * q + 3]);
-        } else {
-#pragma unroll
-            for (int q = 0; q < 64; ++q)
-                if (ab + q < a.n_inputs) o[q] = (uint8_t)(d[q >> 2] >> (8 * (q & 3)));
+                for (int k = 0; k < 16; ++k)
+                    if (ab + k < a.n_inputs) o[k] = (uint8_t)(dw[k >> 2] >> (8 * (k & 3)));
+            }
         }
     }
 }
