@@ -66,8 +66,15 @@ typedef enum {
 
 /* Plan flags. */
 #define XCORR_FLAG_NO_XCD_MAP 0x2u /* dispatch work items in plain order (for tests)  */
+#define XCORR_FLAG_OUT_I32 0x8u   /* int8 path: int32 (re, im) output; see below     */
 #define XCORR_FLAG_NO_PERSIST 0x4u /* one workgroup per work item instead of the
                                       persistent schedule (LDS-DMA tiles; for tests)  */
+/* XCORR_FLAG_OUT_I32: the int8 path writes each visibility as two int32
+ * (re, im) instead of two int64 (8 bytes per baseline, as a complex float
+ * would take).  Exact for any window of at most fold_bound samples between
+ * resets, for both formats (the largest CI8 sums stay below 2^31); a call
+ * that would take a window past fold_bound fails with XCORR_ERR_ARG and
+ * changes nothing.  Not with the fp paths or XCORR_TILE_W4. */
 
 /* Tile variants of the int8 path (xcorr_plan_desc.tile).  All give identical
  * (exact) results; they differ in how samples reach LDS.  The LDS-DMA variants

@@ -73,10 +73,31 @@ LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_str
     a.n_items = p->n_items;
     a.n_blocks = p->n_items * p->n_groups;
     a.xcd_map = p->xcd_map;
+    a.out32 = p->out32;
+    a.reserved = 0;
     a.items = p->d_items;
     a.src = src;
     a.dst = dst;
     return a;
+}
+
+int64_t fold_bound_of(const xcorr_plan_desc* d)
+{
+    // int8 path: int32 partial sums are exact for 65535 samples; fp paths
+    // accumulate in fp32 without a count limit.
+    const int64_t b = d->path == XCORR_PATH_I8_MFMA ? 65535 : (int64_t)1 << 30;
+    // one launch's samples of one channel must stay below 2^31 bytes (the
+    // kernels address a channel through a 32-bit buffer range)
+    const int64_t row = (int64_t)d->n_inputs * (d->format == XCORR_CI4 ? 1 : 2);
+    return std::min<int64_t>(b, ((int64_t)1 << 31) / row - 1);
+}
+
+xcorr_status check_window(const xcorr_plan_s* p, int64_t n_time)
+{
+    if (p->out32 && p->samples + n_time > p->fold_bound)
+        return fail(XCORR_ERR_ARG, "int32 output: window of %lld samples past the bound %lld",
+                    (long long)(p->samples + n_time), (long long)p->fold_bound);
+    return XCORR_OK;
 }
 
 void fill_info(const xcorr_plan_s* p, xcorr_dump_info* info)
@@ -263,7 +284,10 @@ hipError_t launch_w4(const LaunchArgs& a, int grid, hipStream_t s)
     return launch_i8w4(ba, a.xcd_map ? grid : std::min(grid, a.n_blocks), s);
 }
 
-size_t elem_bytes(int path) { return path == XCORR_PATH_I8_MFMA ? 8 : 4; }
+size_t elem_bytes(const xcorr_plan_desc* d)
+{
+    return d->path == XCORR_PATH_I8_MFMA && !(d->flags & XCORR_FLAG_OUT_I32) ? 8 : 4;
+}
 
 xcorr_status check_desc(const xcorr_plan_desc* d)
 {
@@ -280,8 +304,10 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
     if (d->n_inputs % align)
         return fail(XCORR_ERR_UNSUPPORTED, "n_inputs must be a multiple of %d for this format",
                     align);
-    if (d->flags & ~(XCORR_FLAG_NO_XCD_MAP | XCORR_FLAG_NO_PERSIST))
+    if (d->flags & ~(XCORR_FLAG_NO_XCD_MAP | XCORR_FLAG_NO_PERSIST | XCORR_FLAG_OUT_I32))
         return fail(XCORR_ERR_ARG, "unknown flags 0x%x", d->flags);
+    if ((d->flags & XCORR_FLAG_OUT_I32) && (d->path != XCORR_PATH_I8_MFMA || d->tile == kTileW4))
+        return fail(XCORR_ERR_UNSUPPORTED, "int32 output exists for the int8 path (not the W4 tile)");
     if (d->tile < 0 || d->tile > kTileW4) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
     if (d->tile != kTileDefault && d->path != XCORR_PATH_I8_MFMA)
         return fail(XCORR_ERR_UNSUPPORTED, "tile variants exist for the int8 path only");
@@ -294,7 +320,7 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
 size_t plan_device_bytes(const xcorr_plan_desc* d, size_t n_items)
 {
     const int64_t n_b = (int64_t)d->n_inputs * (d->n_inputs + 1) / 2;
-    return (size_t)n_b * d->n_channels * 2 * elem_bytes(d->path) + n_items * sizeof(WorkItem) + 256 + 32;
+    return (size_t)n_b * d->n_channels * 2 * elem_bytes(d) + n_items * sizeof(WorkItem) + 256 + 32;
 }
 
 xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
@@ -389,18 +415,13 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
     p->device = dev;
     p->stream = (hipStream_t)d->stream;
     p->n_b = (int64_t)d->n_inputs * (d->n_inputs + 1) / 2;
-    p->out_bytes = (size_t)p->n_b * d->n_channels * 2 * elem_bytes(d->path);
+    p->out_bytes = (size_t)p->n_b * d->n_channels * 2 * elem_bytes(d);
     p->xcd_map = (d->flags & XCORR_FLAG_NO_XCD_MAP) ? 0 : 1;
+    p->out32 = (d->flags & XCORR_FLAG_OUT_I32) ? 1 : 0;
     // LDS-DMA chunks run as a persistent launch of one workgroup per CU
     const int n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     p->persist_grid = (d->flags & XCORR_FLAG_NO_PERSIST) ? 0 : (n_cu + 7) / 8 * 8;
-    // int8 path: int32 partial sums are exact for 65535 samples; fp paths
-    // accumulate in fp32 without a count limit.
-    p->fold_bound = d->path == XCORR_PATH_I8_MFMA ? 65535 : (int64_t)1 << 30;
-    // one launch's samples of one channel must stay below 2^31 bytes (the
-    // kernels address a channel through a 32-bit buffer range)
-    const int64_t row = (int64_t)d->n_inputs * (d->format == XCORR_CI4 ? 1 : 2);
-    p->fold_bound = std::min<int64_t>(p->fold_bound, ((int64_t)1 << 31) / row - 1);
+    p->fold_bound = fold_bound_of(d);
 
     p->tile = d->tile;
     std::vector<WorkItem>& items = p->h_items;
@@ -447,6 +468,7 @@ xcorr_status xcorr_accumulate(xcorr_plan_t p, const void* d_in, int64_t n_time)
     if (n_time < 0) return fail(XCORR_ERR_ARG, "negative n_time");
     if (n_time == 0) return XCORR_OK;
     xcorr_status s = check_ptr(d_in, "d_in");
+    if (s == XCORR_OK) s = check_window(p, n_time);
     if (s != XCORR_OK) return s;
     s = run_window(p, d_in, n_time, nullptr);
     if (s != XCORR_OK) return s;
@@ -482,6 +504,7 @@ xcorr_status xcorr_accumulate_dump(xcorr_plan_t p, const void* d_in, int64_t n_t
     if (s != XCORR_OK) return s;
     if (n_time == 0) return xcorr_dump(p, d_out, reset, info);
     s = check_ptr(d_in, "d_in");
+    if (s == XCORR_OK) s = check_window(p, n_time);
     if (s != XCORR_OK) return s;
     if (reset) {
         // the last launch writes the dump directly; the accumulator restarts
@@ -540,7 +563,7 @@ xcorr_status xcorr_dump_tiles(xcorr_plan_t p, void* d_out, const uint8_t* tile_s
     e = hipMemcpyAsync(p->d_tile_sel, tile_select, nsel, hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess)
         e = launch_dump_tiles(d_out, p->acc, p->acc_valid ? 1 : 0, p->d_tile_sel, p->d.n_inputs, p->d.n_channels,
-                              (int)(2 * elem_bytes(p->d.path)), reset ? 1 : 0, p->stream);
+                              (int)(2 * elem_bytes(&p->d)), reset ? 1 : 0, p->stream);
     if (e != hipSuccess) return hip_fail(e, "tile dump");
     p->n_dumps += 1;
     fill_info(p, info);

@@ -90,7 +90,19 @@ void make_slices(const std::vector<Entry>& es, const int* first, int n_blocks, i
     }
 }
 
+xcorr_status launch_entries_same_width(xcorr_batch_t b, const std::vector<Entry>& es, const xcorr_batch_config& cfg);
+
+// Entries of both output widths go out as one launch per width.
 xcorr_status launch_entries(xcorr_batch_t b, const std::vector<Entry>& es, const xcorr_batch_config& cfg)
+{
+    std::vector<Entry> w64, w32;
+    for (const Entry& e : es) (e.a.out32 ? w32 : w64).push_back(e);
+    xcorr_status s = w64.empty() ? XCORR_OK : launch_entries_same_width(b, w64, cfg);
+    if (s == XCORR_OK && !w32.empty()) s = launch_entries_same_width(b, w32, cfg);
+    return s;
+}
+
+xcorr_status launch_entries_same_width(xcorr_batch_t b, const std::vector<Entry>& es, const xcorr_batch_config& cfg)
 {
     for (size_t e0 = 0; e0 < es.size(); e0 += kMaxBatchEntries) {
         const size_t n = std::min<size_t>(kMaxBatchEntries, es.size() - e0);
@@ -190,6 +202,7 @@ xcorr_status check_step(xcorr_batch_t b, const void* const* d_in, const int64_t*
         if (n_time[k] < 0) return fail(XCORR_ERR_ARG, "negative n_time for plan %zu", k);
         if (n_time[k] > 0) {
             xcorr_status s = check_ptr(d_in[k], "d_in[k]");
+            if (s == XCORR_OK) s = check_window(b->plans[k], n_time[k]);
             if (s != XCORR_OK) return s;
         }
         if (d_out && d_out[k]) {
@@ -466,6 +479,15 @@ xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, 
     if (st != XCORR_OK) return st;
     for (int64_t t = 0; t < n_time; ++t)
         if (gate[t] != 0xFF && gate[t] >= n_gates) return fail(XCORR_ERR_ARG, "gate[%lld] out of range", (long long)t);
+    {
+        std::vector<int64_t> per(n_gates, 0);
+        for (int64_t t = 0; t < n_time; ++t)
+            if (gate[t] != 0xFF) per[gate[t]] += 1;
+        for (int g = 0; g < n_gates; ++g) {
+            st = check_window(plans[g], per[g]);
+            if (st != XCORR_OK) return st;
+        }
+    }
 
     // The samples of each gate are gathered, in time order, into one packed
     // buffer [channel][kept sample][input] held by the first plan (gate g

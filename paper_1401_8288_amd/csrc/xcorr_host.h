@@ -21,6 +21,7 @@ struct xcorr_plan_s {
     int ch_group = 1;
     int n_groups = 0;
     int xcd_map = 1;
+    int out32 = 0;                  // int32 (re, im) output (XCORR_FLAG_OUT_I32)
     int tile = 0;                   // int8 tile variant in use
     int persist_grid = 0;           // persistent workgroups of the LDS-DMA variants, 0 = off
     int* d_counters = nullptr;      // 8 work counters for batched launches over this plan
@@ -47,6 +48,11 @@ int64_t row_bytes_of(const xcorr_plan_s* p);
 LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
                       const void* src, void* dst);
 void fill_info(const xcorr_plan_s* p, xcorr_dump_info* info);
+// XCORR_ERR_ARG if adding n_time samples would take an int32-output plan's
+// window past its fold bound.
+xcorr_status check_window(const xcorr_plan_s* p, int64_t n_time);
+// Most samples one launch may take (int32 partials, 32-bit buffer ranges).
+int64_t fold_bound_of(const xcorr_plan_desc* d);
 // Enqueues the launches that accumulate n_time samples of every channel
 // (channel c's rows start at in + c * chan_stride), split at the fold bound.
 // If final_dst is non-null the last launch writes its result there instead

@@ -542,7 +542,7 @@ __device__ __forceinline__ void pipeline_group(int k0, Stager<FMT>& st, const Bu
 // persistent workgroup passes the stager of its next item (has_next, nst): its
 // first steps are copied before this item's epilogue, and the next item then
 // starts with issue_prologue = false.
-template <int FMT, int KIND>
+template <int FMT, int KIND, int O32>
 __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane,
                                          const Bufs& L, Stager<FMT>& st, bool has_next, const Stager<FMT>& nst,
                                          bool issue_prologue)
@@ -645,6 +645,17 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
                 int64_t re = ((int64_t)c.re[bi][bj][r]) >> shift;
                 int64_t im = ((int64_t)c.ba[bi][bj][r] - (int64_t)c.ab[bi][bj][r]) >> shift;
                 const int64_t idx = ((int64_t)ch * nb + (int64_t)i * (i + 1) / 2 + j) * 2;
+                if constexpr (O32 != 0) {
+                    // int32 results: exact within the window bound the host enforces
+                    int2 o = make_int2((int)re, (int)im);
+                    if (src) {
+                        const int2 s = *((const int2*)src + idx / 2);
+                        o.x += s.x;
+                        o.y += s.y;
+                    }
+                    *((int2*)dst + idx / 2) = o;
+                    continue;
+                }
                 if (src) {
                     const longlong2 s = *(const longlong2*)(src + idx);
                     re += s.x;
@@ -679,32 +690,32 @@ __device__ __forceinline__ Bufs lds_buffers()
 
 // One work item (local index b of the launch arguments a) by the whole
 // workgroup.
-template <int FMT>
+template <int FMT, int O32>
 __device__ __forceinline__ void dispatch_kind(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane,
                                               const Bufs& L, Stager<FMT>& st, bool has_next,
                                               const Stager<FMT>& nst, bool issue_prologue)
 {
     switch (w.kind) {
-    case KIND_HALF0:  run_tile<FMT, KIND_HALF0>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_HALF1:  run_tile<FMT, KIND_HALF1>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_DIAG_A: run_tile<FMT, KIND_DIAG_A>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_DIAG_B: run_tile<FMT, KIND_DIAG_B>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_QUART0: run_tile<FMT, KIND_QUART0>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_QUART1: run_tile<FMT, KIND_QUART1>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_QUART2: run_tile<FMT, KIND_QUART2>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_QUART3: run_tile<FMT, KIND_QUART3>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    default:          run_tile<FMT, KIND_NONE>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_HALF0:  run_tile<FMT, KIND_HALF0, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_HALF1:  run_tile<FMT, KIND_HALF1, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_DIAG_A: run_tile<FMT, KIND_DIAG_A, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_DIAG_B: run_tile<FMT, KIND_DIAG_B, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_QUART0: run_tile<FMT, KIND_QUART0, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_QUART1: run_tile<FMT, KIND_QUART1, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_QUART2: run_tile<FMT, KIND_QUART2, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_QUART3: run_tile<FMT, KIND_QUART3, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    default:          run_tile<FMT, KIND_NONE, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
     }
 }
 
-template <int FMT>
+template <int FMT, int O32>
 __device__ __forceinline__ void process_item(const LaunchArgs& a, int b, const Bufs& L)
 {
     const WaveJobT<kWaves> w = wave_job<kWaves>(a, b);
     const int lane = threadIdx.x & 63;
     Stager<FMT> st;
     st.init(a, w, lane);
-    dispatch_kind<FMT>(a, w, lane, L, st, false, st, true);
+    dispatch_kind<FMT, O32>(a, w, lane, L, st, false, st, true);
 }
 
 __device__ __forceinline__ int entry_of(const BatchArgs& ba, int g)
@@ -715,13 +726,13 @@ __device__ __forceinline__ int entry_of(const BatchArgs& ba, int g)
 }
 
 // One workgroup per work item of one plan's time chunk.
-template <int FMT>
+template <int FMT, int O32>
 __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_kernel(LaunchArgs a)
 {
     const Bufs L = lds_buffers<FMT>();
     const int b = work_item_index(blockIdx.x, a.n_blocks, a.xcd_map);
     if (b >= a.n_blocks) return;
-    process_item<FMT>(a, b, L);
+    process_item<FMT, O32>(a, b, L);
 }
 
 // Persistent launch over the work items of several plans (subarrays of uneven
@@ -729,7 +740,7 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_kernel(LaunchArgs a)
 // owns the slice [slice[x], slice[x+1]) (contiguous, so a channel's workgroups
 // share that XCD's L2) and its workgroups take items from it in order through
 // the XCD's counter.  Every workgroup leaves once its slice is exhausted.
-template <int FMT>
+template <int FMT, int O32>
 __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_batch_kernel(BatchArgs ba)
 {
     const Bufs L = lds_buffers<FMT>();
@@ -745,7 +756,7 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_batch_kernel(BatchArgs b
         __syncthreads();
         if (g >= hi) break;
         const int e = entry_of(ba, g);
-        process_item<FMT>(ba.e[e], g - ba.first[e], L);
+        process_item<FMT, O32>(ba.e[e], g - ba.first[e], L);
     }
 }
 
@@ -753,7 +764,7 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_batch_kernel(BatchArgs b
 // slice[x] + j, slice[x] + j + P, ... (P workgroups per XCD; a static
 // schedule needs no atomics, so the next item is known in advance) and copies
 // the next item's first steps while it finishes the current one.
-template <int FMT>
+template <int FMT, int O32>
 __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_persist_kernel(BatchArgs ba)
 {
     static_assert(is_dma(FMT), "persistent schedule of the LDS-DMA variants");
@@ -782,7 +793,7 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_persist_kernel(BatchArgs
             wn = wave_job<kWaves>(ba.e[en], gn - ba.first[en]);
             nst.init(ba.e[en], wn, lane);
         }
-        dispatch_kind<FMT>(ba.e[e], w, lane, L, st, has_next, nst, issue);
+        dispatch_kind<FMT, O32>(ba.e[e], w, lane, L, st, has_next, nst, issue);
         if (!has_next) break;
         g = gn;
         e = en;
@@ -796,17 +807,24 @@ template <int FMT>
 hipError_t launch_variant(const LaunchArgs& a, hipStream_t s)
 {
     const dim3 grid(launch_blocks(a.n_blocks, a.xcd_map)), block(kThreads);
-    hipLaunchKernelGGL(xcorr_i8_kernel<FMT>, grid, block, 0, s, a);
+    if (a.out32) hipLaunchKernelGGL((xcorr_i8_kernel<FMT, 1>), grid, block, 0, s, a);
+    else         hipLaunchKernelGGL((xcorr_i8_kernel<FMT, 0>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
+// Every entry of a batched launch has the same output width (the host
+// splits mixed batches).
 template <int FMT>
 hipError_t launch_batch_variant(const BatchArgs& ba, int grid, hipStream_t s)
 {
-    if constexpr (is_dma(FMT))
-        hipLaunchKernelGGL(xcorr_i8_persist_kernel<FMT>, dim3(grid), dim3(kThreads), 0, s, ba);
-    else
-        hipLaunchKernelGGL(xcorr_i8_batch_kernel<FMT>, dim3(grid), dim3(kThreads), 0, s, ba);
+    const bool o32 = ba.e[0].out32 != 0;
+    if constexpr (is_dma(FMT)) {
+        if (o32) hipLaunchKernelGGL((xcorr_i8_persist_kernel<FMT, 1>), dim3(grid), dim3(kThreads), 0, s, ba);
+        else     hipLaunchKernelGGL((xcorr_i8_persist_kernel<FMT, 0>), dim3(grid), dim3(kThreads), 0, s, ba);
+    } else {
+        if (o32) hipLaunchKernelGGL((xcorr_i8_batch_kernel<FMT, 1>), dim3(grid), dim3(kThreads), 0, s, ba);
+        else     hipLaunchKernelGGL((xcorr_i8_batch_kernel<FMT, 0>), dim3(grid), dim3(kThreads), 0, s, ba);
+    }
     return hipGetLastError();
 }
 
@@ -826,8 +844,7 @@ hipError_t launch_persist_single(const LaunchArgs& a, int grid, hipStream_t s)
     const int per = (a.n_blocks / a.n_items + 7) / 8 * a.n_items;
     for (int x = 0; x <= 8; ++x) ba.slice[x] = x * per < a.n_blocks ? x * per : a.n_blocks;
     const int g = a.xcd_map ? grid : (a.n_blocks < grid ? a.n_blocks : grid);
-    hipLaunchKernelGGL(xcorr_i8_persist_kernel<FMT>, dim3(g), dim3(kThreads), 0, s, ba);
-    return hipGetLastError();
+    return launch_batch_variant<FMT>(ba, g, s);
 }
 
 int variant_of(int fmt, int n_inputs, int tile)

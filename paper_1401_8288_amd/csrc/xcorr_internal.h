@@ -70,6 +70,8 @@ struct LaunchArgs {
     int32_t n_items;               // work items per group
     int32_t n_blocks;              // total work items of the launch
     int32_t xcd_map;               // 1: XCD-aware block -> item mapping
+    int32_t out32;                 // 1: int32 (re, im) results and accumulator, else int64
+    int32_t reserved;
     const WorkItem* items;
     const void* src;               // optional accumulator to add (same layout as dst)
     void* dst;                     // result: [channel][tri][2]

@@ -342,6 +342,8 @@ xcorr_status xcorr_server_submit(xcorr_server_t s, int32_t sid, const void* d_in
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->streams.find(sid);
     if (it == s->streams.end() || it->second.closing) return fail(XCORR_ERR_ARG, "unknown or closed stream %d", sid);
+    if ((it->second.desc.flags & XCORR_FLAG_OUT_I32) && n_time > fold_bound_of(&it->second.desc))
+        return fail(XCORR_ERR_ARG, "int32 output: window of %lld samples past the bound", (long long)n_time);
     const int64_t t = s->next_ticket++;
     Ticket& tk = s->tickets[t];
     tk.t_submit = now_ms();

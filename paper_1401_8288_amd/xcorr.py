@@ -21,6 +21,7 @@ CI4, CI8 = 0, 1
 PATH_I8, PATH_F16, PATH_F32 = 0, 1, 2
 FLAG_NO_XCD_MAP = 0x2
 FLAG_NO_PERSIST = 0x4
+FLAG_OUT_I32 = 0x8
 TILE_DEFAULT, TILE_DMA8, TILE_DMA4, TILE_REGS = 0, 1, 2, 3
 
 FORMATS = {"ci4": CI4, "ci8": CI8}
@@ -169,9 +170,9 @@ def make_desc(n_inputs, n_channels, fmt="ci4", path="i8", stream=None, flags=0, 
                     ctypes.c_void_p(sp), int(flags), int(tile))
 
 
-def plan_bytes(n_inputs, n_channels, fmt="ci4", path="i8") -> int:
+def plan_bytes(n_inputs, n_channels, fmt="ci4", path="i8", flags=0, tile=0) -> int:
     out = ctypes.c_size_t(0)
-    _check(lib.xcorr_plan_bytes(ctypes.byref(make_desc(n_inputs, n_channels, fmt, path)),
+    _check(lib.xcorr_plan_bytes(ctypes.byref(make_desc(n_inputs, n_channels, fmt, path, flags=flags, tile=tile)),
                                 ctypes.byref(out)))
     return int(out.value)
 
@@ -193,6 +194,7 @@ class Plan:
     def __init__(self, n_inputs: int, n_channels: int, fmt: str = "ci4", path: str = "i8",
                  stream: torch.cuda.Stream | None = None, flags: int = 0, tile: int = 0):
         self.n_inputs, self.n_channels, self.fmt, self.path = n_inputs, n_channels, fmt, path
+        self.out32 = bool(flags & FLAG_OUT_I32)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.device = self.stream.device
         desc = make_desc(n_inputs, n_channels, fmt, path, self.stream, flags, tile)
@@ -205,7 +207,9 @@ class Plan:
     # ---------------------------------------------------------------- helpers
     @property
     def out_dtype(self):
-        return torch.int64 if self.path == "i8" else torch.float32
+        if self.path != "i8":
+            return torch.float32
+        return torch.int32 if self.out32 else torch.int64
 
     def out_shape(self):
         return (self.n_channels, self.n_baselines, 2)
@@ -443,26 +447,26 @@ class Server:
         self._h = h
         self._streams = {}
 
-    def open(self, n_inputs: int, n_channels: int, fmt: str = "ci4", tile: int = 0) -> int:
-        desc = make_desc(n_inputs, n_channels, fmt, "i8", tile=tile)
+    def open(self, n_inputs: int, n_channels: int, fmt: str = "ci4", tile: int = 0, flags: int = 0) -> int:
+        desc = make_desc(n_inputs, n_channels, fmt, "i8", tile=tile, flags=flags)
         sid = ctypes.c_int32(0)
         _check(lib.xcorr_server_open(self._h, ctypes.byref(desc), ctypes.byref(sid)))
-        self._streams[sid.value] = (n_inputs, n_channels, fmt)
+        self._streams[sid.value] = (n_inputs, n_channels, fmt, torch.int32 if flags & FLAG_OUT_I32 else torch.int64)
         return sid.value
 
     def new_output(self, sid: int) -> torch.Tensor:
-        n, c, _ = self._streams[sid]
-        return torch.empty((c, n * (n + 1) // 2, 2), dtype=torch.int64, device=self.stream.device)
+        n, c, _, dt = self._streams[sid]
+        return torch.empty((c, n * (n + 1) // 2, 2), dtype=dt, device=self.stream.device)
 
     def submit(self, sid: int, x: torch.Tensor, out: torch.Tensor) -> int:
-        n, c, fmt = self._streams[sid]
+        n, c, fmt, dt = self._streams[sid]
         if not x.is_contiguous() or x.shape[0] != c or x.shape[2] != n:
             raise ValueError("input does not match stream %d" % sid)
         if fmt == "ci4" and (x.dtype != torch.uint8 or x.dim() != 3):
             raise ValueError("ci4 input must be uint8 [channel][time][input]")
         if fmt == "ci8" and (x.dtype != torch.int8 or x.dim() != 4):
             raise ValueError("ci8 input must be int8 [channel][time][input][2]")
-        if (out.dtype != torch.int64 or not out.is_contiguous()
+        if (out.dtype != dt or not out.is_contiguous()
                 or tuple(out.shape) != (c, n * (n + 1) // 2, 2)):
             raise ValueError("output does not match stream %d" % sid)
         t = ctypes.c_int64(0)

@@ -206,3 +206,15 @@ def test_fstage_argument_checks():
     assert nb.value == 4 * 2 * 32                     # channels 5..24 -> rows of 0..31
     assert L.xcorr_fstage_work_bytes(ctypes.byref(xcorr.FstageDesc(**dict(ok, out_kind=1))),
                                      3 * 8192, ctypes.byref(nb)) == 0 and nb.value == 0
+
+
+def test_int32_output_flag_checks():
+    from paper_1401_8288_amd import xcorr
+    full = xcorr.plan_bytes(512, 64, "ci4", "i8")
+    half = xcorr.plan_bytes(512, 64, "ci4", "i8", flags=xcorr.FLAG_OUT_I32)
+    nb = 512 * 513 // 2 * 64 * 2
+    assert full - half == nb * 4                     # int32 instead of int64 pairs
+    for path, tile in (("f16", 0), ("f32", 0), ("i8", 4)):
+        with pytest.raises(xcorr.XcorrError) as e:
+            xcorr.plan_bytes(512, 64, "ci4", path, flags=xcorr.FLAG_OUT_I32, tile=tile)
+        assert e.value.status == -6
