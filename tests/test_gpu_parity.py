@@ -331,3 +331,15 @@ def test_large_n_fp_paths_error_bound(path):
     bound = w.n_time * 2.0 ** -24 * scale
     say("%s: max abs err %.1f, max err / sqrt(Vii Vjj) %.3e" % (path, err.max(), (err / scale).max()))
     assert (err <= bound).all()
+
+
+@pytest.mark.parametrize("fmt", ["ci4", "ci8"])
+def test_many_inputs_one_channel(fmt):
+    # 4096 inputs: 64 row blocks, 2080 tiles per channel (8.4 M baselines)
+    say("many inputs", fmt)
+    x = synth.random_input(1, 70, 4096, fmt, seed=41, device=DEV)
+    ref = oracle.correlate(x.cpu().numpy(), fmt)
+    got, info = run(x, fmt, "i8")
+    np.testing.assert_array_equal(got, ref)
+    got32, _ = run(x, fmt, "i8", flags=xc().FLAG_OUT_I32)
+    np.testing.assert_array_equal(got32.astype(np.int64), ref)
