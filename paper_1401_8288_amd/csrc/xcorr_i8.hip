@@ -60,15 +60,19 @@ __host__ __device__ constexpr int dma_depth(int v) { return v == V_CI4_DMA8 ? 8 
 // workgroups of the channel, which run at the same time on the same XCD, wait
 // for the same lines.
 constexpr int kPrefetch = 4;
+// CI8 stages twice the bytes per thread: three steps ahead keep its loads in
+// registers without spilling.
+template <int FMT>
+constexpr int kRing = FMT == V_CI8 ? 3 : kPrefetch;
 // V_CI4_DMA*: LDS buffers, one per step in flight; the copy of step k + depth
 // is issued while step k runs.
 template <int FMT>
-__device__ __forceinline__ constexpr int ring_depth() { return kPrefetch; }
+__device__ __forceinline__ constexpr int ring_depth() { return kRing<FMT>; }
 template <int FMT>
 __device__ __forceinline__ constexpr int n_buffers() { return is_dma(FMT) ? dma_depth(FMT) : 3; }
 // Steps per unrolled loop iteration.
 template <int FMT>
-__device__ __forceinline__ constexpr int group_steps() { return is_dma(FMT) ? dma_depth(FMT) : kPrefetch; }
+__device__ __forceinline__ constexpr int group_steps() { return is_dma(FMT) ? dma_depth(FMT) : kRing<FMT>; }
 
 // LDS geometry.  CI4: one part per slot, the raw bytes (re and im nibbles)
 // of 64 samples x 64 inputs, rows of 64 bytes padded to kPitch.  CI8: two
@@ -91,7 +95,7 @@ struct Geo {
 template <int FMT>
 struct Stager {
     static constexpr int kJobs = (FMT == V_CI4) ? 1 : 2;
-    uint32_t r[kPrefetch][kJobs][8];  // ring: slot k % kPrefetch holds step k
+    uint32_t r[kRing<FMT>][kJobs][8];  // ring: slot k % depth holds step k
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t vofs[kJobs];
     int row[kJobs];
@@ -465,10 +469,10 @@ __device__ __forceinline__ void schedule_step()
 }
 
 // V_CI4 and V_CI8: three LDS buffers, step k in buffer k % 3.  CI4 step k:
-// load the samples of step k + kPrefetch into ring slot S = k % kPrefetch,
+// load the samples of step k + D into ring slot S = k % D (D = 4; 3 for CI8),
 // read the raw fragments of step k+1, run the MFMAs of step k from
 // registers, split the step-k+1 fragments into operands, and write step k+2
-// (ring slot (S+2) % kPrefetch) into buffer (k+2) % 3.  The MFMAs are
+// (ring slot (S+2) % D) into buffer (k+2) % 3.  The MFMAs are
 // interleaved with the independent vector work of the next steps.  Buffer
 // (k+2) % 3 last held step k-1, whose fragments were read in step k-2;
 // buffer (k+1) % 3 was written in step k-1.  CI8 fragments are twice as
@@ -592,13 +596,13 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
         }
         dma_barrier<2 * (D - 2)>();
     } else {
-        // Samples of steps 0..kPrefetch-1 into the ring, steps 0 and 1 into
+        // Samples of steps 0..depth-1 into the ring, steps 0 and 1 into
         // LDS buffers 0 and 1, operands of step 0 (CI4).
-        static_assert(kPrefetch == 4, "the unrolled ring below assumes four slots");
+        static_assert(kRing<FMT> == 3 || kRing<FMT> == 4, "ring of three or four slots");
         st.template load<0>(0);
         st.template load<1>(1);
         st.template load<2>(2);
-        st.template load<3>(3);
+        if constexpr (kRing<FMT> == 4) st.template load<3>(3);
         st.template store<0>(lds);
         st.template store<1>(lds + Geo<FMT>::kBufBytes);
         __syncthreads();
