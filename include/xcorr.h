@@ -77,8 +77,12 @@ typedef enum {
  * changes nothing.  Not with the fp paths or XCORR_TILE_W4. */
 
 /* Tile variants of the int8 path (xcorr_plan_desc.tile).  All give identical
- * (exact) results; they differ in how samples reach LDS.  The LDS-DMA variants
- * need XCORR_CI4 and n_inputs % 16 == 0. */
+ * (exact) results; they differ in how samples reach LDS. */
+/* LDS-DMA tiles need n_inputs % 16 == 0.  With 8-bit samples a single plan
+ * first splits each chunk's rows into real and imaginary planes (one HBM
+ * pass into a staging buffer the plan holds and grows to its largest chunk,
+ * which xcorr_plan_bytes does not count); batches of 8-bit plans use the
+ * register tile.  DMA8 and W4 take 4-bit samples only. */
 #define XCORR_TILE_DEFAULT 0       /* LDS-DMA depth 4 where allowed, else registers */
 #define XCORR_TILE_DMA8 1          /* buffer loads straight to LDS, 8 steps in flight */
 #define XCORR_TILE_DMA4 2          /* the same, 4 steps in flight                   */

@@ -311,9 +311,10 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
     if (d->tile < 0 || d->tile > kTileW4) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
     if (d->tile != kTileDefault && d->path != XCORR_PATH_I8_MFMA)
         return fail(XCORR_ERR_UNSUPPORTED, "tile variants exist for the int8 path only");
-    if ((d->tile == kTileDma8 || d->tile == kTileDma4 || d->tile == kTileW4) &&
-        (d->format != XCORR_CI4 || d->n_inputs % 16))
-        return fail(XCORR_ERR_UNSUPPORTED, "LDS-DMA tiles need 4-bit samples and n_inputs %% 16 == 0");
+    if ((d->tile == kTileDma8 || d->tile == kTileDma4 || d->tile == kTileW4) && d->n_inputs % 16)
+        return fail(XCORR_ERR_UNSUPPORTED, "LDS-DMA tiles need n_inputs %% 16 == 0");
+    if ((d->tile == kTileDma8 || d->tile == kTileW4) && d->format != XCORR_CI4)
+        return fail(XCORR_ERR_UNSUPPORTED, "the DMA8 and W4 tiles take 4-bit samples");
     return XCORR_OK;
 }
 
@@ -326,8 +327,33 @@ size_t plan_device_bytes(const xcorr_plan_desc* d, size_t n_items)
 xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
                           const void* src, void* dst)
 {
-    const LaunchArgs a = chunk_args(p, in, chan_stride, t_len, src, dst);
+    LaunchArgs a = chunk_args(p, in, chan_stride, t_len, src, dst);
     hipError_t e;
+    if (p->d.path == XCORR_PATH_I8_MFMA && p->d.format == XCORR_CI8 && p->tile != kTileRegs &&
+        p->d.n_inputs % 16 == 0) {
+        // the LDS-DMA kernel reads the chunk with each row split into its
+        // real and imaginary planes: one HBM pass into the plan's staging
+        // buffer (grown to the largest chunk seen)
+        const int64_t row = row_bytes_of(p);
+        const size_t need = (size_t)row * t_len * p->d.n_channels;
+        if (p->planes_bytes < need) {
+            e = hipStreamSynchronize(p->stream);
+            if (e == hipSuccess) {
+                if (p->d_planes) (void)hipFree(p->d_planes);
+                p->d_planes = nullptr;
+                p->planes_bytes = 0;
+                e = hipMalloc((void**)&p->d_planes, need);
+                if (e == hipSuccess) p->planes_bytes = need;
+            }
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(XCORR_ERR_NOMEM, "8-bit plane staging (%zu bytes): %s", need, hipGetErrorString(e));
+            }
+        }
+        e = launch_ci8_planes(in, chan_stride, p->d.n_inputs, t_len, p->d.n_channels, p->d_planes, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "8-bit plane split");
+        a = chunk_args(p, p->d_planes, row * t_len, t_len, src, dst);
+    }
     switch (p->d.path) {
     case XCORR_PATH_I8_MFMA:
         e = p->tile == kTileW4 ? launch_w4(a, p->persist_grid ? p->persist_grid : 256, p->stream)
@@ -677,6 +703,7 @@ xcorr_status xcorr_destroy(xcorr_plan_t p)
     release(p->d_items);
     release(p->d_counters);
     release(p->d_tile_sel);
+    release(p->d_planes);
     release(p->d_gate_buf);
     release(p->d_gate_idx);
     delete p;

@@ -49,11 +49,17 @@ constexpr int kPitch = 80;                 // LDS bytes per row (64 samples + 16
 // [time][input] order and transposed by the LDS transpose read
 // (ds_read_b64_tr_b8); no vector registers or LDS writes are spent on staging.
 // The DMA variant comes in two copy-pipeline depths (LDS buffers in flight),
-// 4 and 8; the plan's tile setting or the autotuner picks one.
-enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_DMA4 = 2, V_CI4_DMA8 = 3 };
-__host__ __device__ constexpr bool is_ci4(int v) { return v != V_CI8; }
-__host__ __device__ constexpr bool is_dma(int v) { return v == V_CI4_DMA4 || v == V_CI4_DMA8; }
+// 4 and 8; the plan's tile setting or the autotuner picks one.  V_CI8_DMA4:
+// 8-bit samples with n_inputs % 16 == 0 whose rows the host has split into
+// a real and an imaginary plane ([time][re of every input | im of every
+// input]); both planes are copied and transposed like the 4-bit bytes, and
+// their fragments are the MFMA operands as they are.
+enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_DMA4 = 2, V_CI4_DMA8 = 3, V_CI8_DMA4 = 4 };
+__host__ __device__ constexpr bool is_ci4(int v) { return v != V_CI8 && v != V_CI8_DMA4; }
+__host__ __device__ constexpr bool is_dma(int v) { return v == V_CI4_DMA4 || v == V_CI4_DMA8 || v == V_CI8_DMA4; }
 __host__ __device__ constexpr int dma_depth(int v) { return v == V_CI4_DMA8 ? 8 : 4; }
+// LDS-DMA copies one wave issues per step: two per sample plane.
+__host__ __device__ constexpr int dma_copies(int v) { return v == V_CI8_DMA4 ? 4 : 2; }
 
 // Register-staged variants: global loads run kPrefetch steps ahead of the
 // step they feed: a channel's first reader waits for HBM, and the other
@@ -77,9 +83,10 @@ __device__ __forceinline__ constexpr int group_steps() { return is_dma(FMT) ? dm
 // LDS geometry.  CI4: one part per slot, the raw bytes (re and im nibbles)
 // of 64 samples x 64 inputs, rows of 64 bytes padded to kPitch.  CI8: two
 // parts, re rows and im rows.  V_CI4_DMA*: unpadded 64-byte sample rows.
+// V_CI8_DMA4: a buffer is two planes (re, then im) of V_CI4_DMA* slots.
 template <int FMT>
 struct Geo {
-    static constexpr int kParts = FMT == V_CI8 ? 2 : 1;
+    static constexpr int kParts = (FMT == V_CI8 || FMT == V_CI8_DMA4) ? 2 : 1;
     static constexpr int kRowPitch = is_dma(FMT) ? kRowBlock : kPitch;
     static constexpr int kPart = kRowBlock * kRowPitch;
     static constexpr int kSlotBytes = kParts * kPart;
@@ -210,6 +217,41 @@ struct Stager<V_CI4_DMA4> : DmaStager {};
 template <>
 struct Stager<V_CI4_DMA8> : DmaStager {};
 
+// V_CI8_DMA4 staging: the same copies for the real plane (the first
+// n_inputs bytes of a row) into the buffer's first half, and for the
+// imaginary plane (the next n_inputs bytes) into its second half.
+constexpr int kPlaneBytes = kSlots * kRowBlock * kRowBlock;
+struct DmaStager2 : DmaStager {
+    uint32_t vofs_im[2];
+
+    __device__ __forceinline__ void init(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane)
+    {
+        DmaStager::init(a, w, lane);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int row = 32 * w.stage_part + 16 * j + (lane >> 2);
+            const int q = (lane & 3) ^ swz(row);
+            const int input = (w.stage_rb < 0 ? 0 : w.stage_rb) * kRowBlock + 16 * q;
+            vofs_im[j] = (uint32_t)row * (uint32_t)a.row_bytes +
+                         (input < a.n_inputs ? (uint32_t)(a.n_inputs + input) : 0x80000000u);
+        }
+    }
+
+    __device__ __forceinline__ void load(uint8_t* buf, int k) const
+    {
+        typedef __attribute__((address_space(3))) void lds_void;
+        DmaStager::load(buf, k);
+        const uint32_t step = (uint32_t)(k * kStep) * (uint32_t)row_bytes;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc,
+                                                     (lds_void*)(buf + kPlaneBytes + lds_ofs + 16 * kRowBlock * j),
+                                                     16, (int)(vofs_im[j] + step), 0, 0, 0);
+    }
+};
+template <>
+struct Stager<V_CI8_DMA4> : DmaStager2 {};
+
 // Operand fragment of a 16-row block: lane l holds row l % 16 and the 16
 // samples 16 * (l / 16)..+15 of the step (the same sample set for the A and
 // B operands of the MFMA, so the contraction pairs equal samples).
@@ -286,6 +328,10 @@ template <>
 struct Raw<V_CI8> {
     Ops o;
 };
+template <>
+struct Raw<V_CI8_DMA4> {
+    Ops o;
+};
 
 template <int KIND>
 __device__ __forceinline__ constexpr bool same_block(int)
@@ -316,6 +362,15 @@ __device__ __forceinline__ void read_raw(const uint8_t* buf, int si, int sj, int
         if constexpr (FMT == V_CI4) {
             if (need_i<KIND>(b)) r.ri[b] = frag(pI, b, lane);
             if (need_j<KIND>(b)) r.rj[b] = frag(pJ, b, lane);
+        } else if constexpr (FMT == V_CI8_DMA4) {
+            if (need_i<KIND>(b)) {
+                r.o.ia[b] = frag_tr(buf, fo.i[b]);
+                r.o.ib[b] = frag_tr(buf + kPlaneBytes, fo.i[b]);
+            }
+            if (need_j<KIND>(b)) {
+                r.o.ja[b] = frag_tr(buf, fo.j[b]);
+                r.o.jb[b] = frag_tr(buf + kPlaneBytes, fo.j[b]);
+            }
         } else if constexpr (is_dma(FMT)) {
             if (need_i<KIND>(b)) r.ri[b] = frag_tr(buf, fo.i[b]);
             if (need_j<KIND>(b)) r.rj[b] = frag_tr(buf, fo.j[b]);
@@ -429,7 +484,24 @@ template <int FMT, int KIND>
 __device__ __forceinline__ void schedule_step()
 {
     constexpr int nm = 4 * n_blocks<KIND>();
-    if constexpr (is_dma(FMT)) {
+    if constexpr (FMT == V_CI8_DMA4) {
+        // four copies between the first MFMAs, then one pair of fragment
+        // reads after each of the next MFMAs
+        constexpr int n_dsr = 4 * n_frags<KIND>();
+        constexpr int a = nm / 8 > 0 ? nm / 8 : 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            __builtin_amdgcn_sched_group_barrier(0x008, a, 0);    // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);    // VMEM (copy)
+        }
+        constexpr int rest = nm - 4 * a > 0 ? nm - 4 * a : 1;
+        constexpr int rpm = (n_dsr + rest - 1) / rest;
+#pragma unroll
+        for (int m = 0; m < rest; ++m) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, rpm, 0);  // DS read
+        }
+    } else if constexpr (is_dma(FMT)) {
         constexpr int n_dsr = 2 * n_frags<KIND>();
         constexpr int n_valu = 12 * n_frags<KIND>();
         // The copies and fragment reads are spread over the step so that no
@@ -500,7 +572,7 @@ __device__ __forceinline__ void pipeline_step(int k, Stager<FMT>& st, const Bufs
             prepare<FMT, KIND>(raw, nx);
             schedule_step<FMT, KIND>();
         }
-        dma_barrier<2 * (D - 2)>();
+        dma_barrier<dma_copies(FMT) * (D - 2)>();
         ops = nx;
     } else if constexpr (is_ci4(FMT)) {
         constexpr int D = ring_depth<FMT>();
@@ -588,13 +660,13 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
 #pragma unroll
             for (int s = 0; s < D; ++s) st.load(L.p[s], s);
         }
-        dma_barrier<2 * (D - 1)>();
+        dma_barrier<dma_copies(FMT) * (D - 1)>();
         if (KIND != KIND_NONE) {
             Raw<FMT> raw;
             read_raw<FMT, KIND>(lds, si, sj, lane, fo, raw);
             prepare<FMT, KIND>(raw, ops);
         }
-        dma_barrier<2 * (D - 2)>();
+        dma_barrier<dma_copies(FMT) * (D - 2)>();
     } else {
         // Samples of steps 0..depth-1 into the ring, steps 0 and 1 into
         // LDS buffers 0 and 1, operands of step 0 (CI4).
@@ -853,7 +925,7 @@ hipError_t launch_persist_single(const LaunchArgs& a, int grid, hipStream_t s)
 
 int variant_of(int fmt, int n_inputs, int tile)
 {
-    if (fmt == 1) return V_CI8;
+    if (fmt == 1) return (tile == kTileRegs || n_inputs % 16 != 0) ? V_CI8 : V_CI8_DMA4;
     if (tile == kTileRegs || n_inputs % 16 != 0) return V_CI4;
     return tile == kTileDma8 ? V_CI4_DMA8 : V_CI4_DMA4;
 }
@@ -865,6 +937,8 @@ hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, h
     switch (variant_of(fmt, a.n_inputs, tile)) {
     case V_CI8:      return launch_variant<V_CI8>(a, s);
     case V_CI4:      return launch_variant<V_CI4>(a, s);
+    case V_CI8_DMA4: return persist_grid ? launch_persist_single<V_CI8_DMA4>(a, persist_grid, s)
+                                         : launch_variant<V_CI8_DMA4>(a, s);
     case V_CI4_DMA4: return persist_grid ? launch_persist_single<V_CI4_DMA4>(a, persist_grid, s)
                                          : launch_variant<V_CI4_DMA4>(a, s);
     default:         return persist_grid ? launch_persist_single<V_CI4_DMA8>(a, persist_grid, s)
@@ -878,6 +952,9 @@ hipError_t launch_i8_batch(const BatchArgs& ba, int fmt, int tile, int grid, hip
     // n_inputs to be a multiple of 16
     int n16 = 1;
     for (int e = 0; e < ba.n_entries; ++e) n16 &= ba.e[e].n_inputs % 16 == 0;
+    // 8-bit batches stay on the register-staged kernel: the two-plane
+    // layout of V_CI8_DMA4 is made by the single-plan launch path only
+    if (fmt == 1) return launch_batch_variant<V_CI8>(ba, grid, s);
     switch (variant_of(fmt, n16 ? 16 : 4, tile)) {
     case V_CI8:      return launch_batch_variant<V_CI8>(ba, grid, s);
     case V_CI4:      return launch_batch_variant<V_CI4>(ba, grid, s);

@@ -166,5 +166,10 @@ hipError_t launch_f16(const LaunchArgs& a, int fmt, hipStream_t s);
 hipError_t launch_f32(const LaunchArgs& a, int fmt, hipStream_t s);
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// 8-bit samples [channel][time][input][re, im] (channel c at in + c *
+// chan_stride) -> out[channel][time][re of every input, then im of every
+// input] (rows of the same 2 n_inputs bytes); n_inputs % 8 == 0.
+hipError_t launch_ci8_planes(const uint8_t* in, int64_t chan_stride, int n_inputs, int64_t t_len,
+                             int n_channels, uint8_t* out, hipStream_t s);
 
 }  // namespace xcorr

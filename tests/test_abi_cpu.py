@@ -68,7 +68,8 @@ def _desc(**kw):
     (dict(n_inputs=40000), -6),
     (dict(flags=0x100), -1), (dict(tile=7), -1),
     (dict(tile=1, n_inputs=36), -6),    # LDS-DMA tiles need n_inputs % 16 == 0
-    (dict(tile=2, fmt="ci8"), -6),      # ... and 4-bit samples
+    (dict(tile=1, fmt="ci8"), -6),      # DMA8 and W4 take 4-bit samples only
+    (dict(tile=4, fmt="ci8"), -6),
     (dict(tile=3, path="f32"), -6)])    # tile variants exist for the int8 path only
 def test_bad_descriptors_rejected_before_any_device_call(kw, status):
     from paper_1401_8288_amd import xcorr

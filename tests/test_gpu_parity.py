@@ -184,6 +184,36 @@ def test_int8_tile_variants(tile, shape):
     np.testing.assert_array_equal(got, ref)
 
 
+@pytest.mark.parametrize("tile", [2, 3])
+@pytest.mark.parametrize("shape", [(64, 3, 1000), (512, 1, 333), (112, 5, 64), (16, 7, 129), (48, 5, 300),
+                                   (192, 2, 65), (400, 2, 77)], ids=lambda s: "x".join(map(str, s)))
+def test_int8_tile_variants_8bit(tile, shape):
+    # 8-bit samples: the LDS-DMA tile (rows split into re | im planes first)
+    # and the register tile, full value range
+    n_in, n_ch, n_t = shape
+    say("tile ci8", tile, shape)
+    x = synth.random_input(n_ch, n_t, n_in, "ci8", seed=tile + 3 * n_in, lo=-128, hi=127, device=DEV)
+    ref = oracle.correlate(x.cpu().numpy(), "ci8")
+    got, _ = run(x, "ci8", "i8", tile=tile)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_8bit_plan_reuses_and_grows_its_plane_staging():
+    # windows of growing and shrinking length through one 8-bit LDS-DMA plan
+    X = xc()
+    p = X.Plan(64, 3, "ci8", "i8", tile=2)
+    total = None
+    xs = [synth.random_input(3, n_t, 64, "ci8", seed=n_t, device=DEV) for n_t in (100, 700, 300)]
+    for x in xs:
+        p.accumulate(x)
+    out, info = p.dump()
+    torch.cuda.synchronize()
+    ref = sum(oracle.correlate(x.cpu().numpy(), "ci8") for x in xs)
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+    assert info.samples_accumulated == 1100
+    p.close()
+
+
 @pytest.mark.parametrize("fmt,re,im,per_sample", [("ci4", -8, -8, 128), ("ci8", -128, -128, 32768),
                                                   ("ci8", 127, -128, 127 * 127 + 128 * 128)])
 def test_int32_fold_past_two_to_the_31(fmt, re, im, per_sample):
