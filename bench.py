@@ -294,6 +294,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the fp16 / fp32 kernels")
     ap.add_argument("--no-corner-turn", action="store_true", help="skip the corner-turn leg")
     ap.add_argument("--no-fstage", action="store_true", help="skip the F-stage leg")
+    ap.add_argument("--workload", default="lwa",
+                    help="synthetic workload of the timed window (default lwa, the headline; others for profiling)")
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="length of the batched-streaming leg (0 skips it)")
     ap.add_argument("--serving-speedup", type=float, default=40.0,
@@ -315,7 +317,7 @@ def main():
     from paper_1401_8288_amd import synth, xcorr
 
     dev = torch.device("cuda:0")
-    w = synth.WORKLOADS["lwa"]
+    w = synth.WORKLOADS[args.workload]
     log("generating", w.name, w.n_inputs, "inputs x", w.n_channels, "channels x", w.n_time, "samples")
     x = synth.generate(w, device=dev)
     torch.cuda.synchronize()
@@ -345,8 +347,10 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int8", "data": "synthetic (seeded, generated on device)",
-        "config": {"workload": "lwa: 256 antennas x 2 pol = 512 inputs, 4096 channels, "
-                               "4096 samples/integration, 4+4-bit complex",
+        "config": {"workload": ("lwa: 256 antennas x 2 pol = 512 inputs, 4096 channels, "
+                                "4096 samples/integration, 4+4-bit complex") if w.name == "lwa" else
+                               "%s: %d inputs, %d channels, %d samples/integration, %s"
+                               % (w.name, w.n_inputs, w.n_channels, w.n_time, w.fmt),
                    "n_inputs": w.n_inputs, "n_channels": w.n_channels, "n_time": w.n_time,
                    "format": w.fmt,
                    "path": "int8 MFMA, int32 partials, int32 (re, im) output, bit-exact (window <= 65535 samples)",
@@ -354,7 +358,8 @@ def main():
                    "work_items": info.work_items},
         "int64_output": {"ms_per_step": round(ms64, 4), "value": round(cmac / (ms64 * 1e-3) / 1e12, 3),
                          "pct_int8_peak": round(100 * tops64 / PEAK_INT8_TOPS, 2)},
-        "roofline": {"bound": "mfma", "kernel": "xcorr_i8_persist_kernel<V_CI4_DMA4, int32 out>",
+        "roofline": {"bound": "mfma",
+                     "kernel": "xcorr_i8_persist_kernel<V_%s_DMA4, int32 out>" % w.fmt.upper(),
                      "achieved": round(tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
                      "frac": round(tops / PEAK_INT8_TOPS, 4), "traffic": None,
                      "algorithmic_ops_per_launch": 8 * cmac,
@@ -362,7 +367,7 @@ def main():
                      "hbm_gbs_algorithmic": round(hbm_bytes / (ms * 1e-3) / 1e9, 1)},
         "pct_int8_peak": round(100 * tops / PEAK_INT8_TOPS, 2),
     }
-    traffic, how = read_traffic()
+    traffic, how = read_traffic() if w.name == "lwa" else (None, "counters recorded for the lwa workload only")
     result["roofline"]["traffic"] = traffic
     result["roofline"]["traffic_source"] = how
     torch.cuda.empty_cache()
@@ -386,12 +391,12 @@ def main():
         result["compare"] = comp
         torch.cuda.empty_cache()
 
-    if not args.no_corner_turn:
+    if not args.no_corner_turn and w.name == "lwa":
         log("corner turn at the same size")
         result["corner_turn"] = corner_turn_leg(torch, xcorr, w)
         log("corner turn:", result["corner_turn"])
 
-    if not args.no_fstage:
+    if not args.no_fstage and w.name == "lwa":
         log("F-stage making the same workload")
         result["fstage"] = fstage_leg(torch, xcorr, w)
         log("F-stage:", result["fstage"])
