@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(kThreads) fstage_transpose_kernel(FstageArgs a
 {
     __shared__ uint32_t T[32][128 + 4];
     const int t = threadIdx.x;
-    const int n_ct = (a.cp + 127) / 128, n_at = (a.n_inputs + 127) / 128;
+    const int n_ct = (a.cp + 127) / 128;
     // spectra vary fastest over the grid: workgroups running together touch
     // neighbouring rows of both buffers (few pages)
     int b = blockIdx.x;
