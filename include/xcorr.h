@@ -81,8 +81,11 @@ typedef enum {
 /* LDS-DMA tiles need n_inputs % 16 == 0.  With 8-bit samples a single plan
  * first splits each chunk's rows into real and imaginary planes (one HBM
  * pass into a staging buffer the plan holds and grows to its largest chunk,
- * which xcorr_plan_bytes does not count); batches of 8-bit plans use the
- * register tile.  DMA8 and W4 take 4-bit samples only. */
+ * which xcorr_plan_bytes does not count).  Growing it waits for the plan's
+ * stream and allocates, so a call that would grow it cannot run under
+ * stream capture; one window of the largest size first avoids that.
+ * Batches of 8-bit plans use the register tile.  DMA8 and W4 take 4-bit
+ * samples only. */
 #define XCORR_TILE_DEFAULT 0       /* LDS-DMA depth 4 where allowed, else registers */
 #define XCORR_TILE_DMA8 1          /* buffer loads straight to LDS, 8 steps in flight */
 #define XCORR_TILE_DMA4 2          /* the same, 4 steps in flight                   */
