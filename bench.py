@@ -334,6 +334,9 @@ def main():
     out_bytes_i32 = w.output_bytes // 2
     hbm_bytes = w.input_bytes + out_bytes_i32
     log("int8, int32 out: %.3f ms/window, %.1f TCMAC/s, %.1f%% of int8 peak" % (ms, tcmac, 100 * tops / PEAK_INT8_TOPS))
+    # the exact result, kept as float32 (exact below 2^24) to measure the
+    # fp paths' error over every entry of the window
+    exact = out.to(torch.float32) if (not args.no_compare and int(out.abs().max()) < 2 ** 24) else None
     del out
     torch.cuda.empty_cache()
     log("int8 MFMA path, int64 output: %d warmup + %d timed windows" % (args.warmup, args.steps))
@@ -380,15 +383,18 @@ def main():
                                         ("f32", 2, PEAK_FP32_TFLOPS, "TFLOP/s")):
             log("%s path: 1 warmup + %d timed windows" % (path, steps))
             pms, pout, _ = time_path(torch, xcorr, x, w, path, steps, 1)
+            err = float((pout - exact).abs().max()) if exact is not None else None
             del pout
             ptc = cmac / (pms * 1e-3) / 1e12
             comp[path] = {"ms_per_step": round(pms, 3), "tcmac_s": round(ptc, 3),
                           "achieved": round(8 * cmac / (pms * 1e-3) / 1e12, 2), "peak": peak,
-                          "unit": unit, "frac": round(8 * cmac / (pms * 1e-3) / 1e12 / peak, 4)}
+                          "unit": unit, "frac": round(8 * cmac / (pms * 1e-3) / 1e12 / peak, 4),
+                          "max_abs_err_vs_exact": err}
             log("%s: %.3f ms/window, %.2f TCMAC/s" % (path, pms, ptc))
         comp["speedup_int8_vs_fp32"] = round(comp["f32"]["ms_per_step"] / ms, 2)
         comp["speedup_int8_vs_fp16"] = round(comp["f16"]["ms_per_step"] / ms, 2)
         result["compare"] = comp
+        exact = None
         torch.cuda.empty_cache()
 
     if not args.no_corner_turn and w.name == "lwa":
