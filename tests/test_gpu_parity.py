@@ -88,6 +88,18 @@ def test_ragged_shapes_full_range(fmt, shape, path):
         np.testing.assert_array_equal(got, ref.astype(np.float32))
 
 
+@pytest.mark.parametrize("fmt", ["ci4", "ci8"])
+def test_launch_modes_give_the_same_result(fmt):
+    # persistent or one workgroup per item, XCD-aware or plain order: the
+    # same exact sums (both LDS-DMA variants)
+    X = xc()
+    x = synth.random_input(6, 333, 128, fmt, seed=17, device=DEV)
+    ref = oracle.correlate(x.cpu().numpy(), fmt)
+    for flags in (0, X.FLAG_NO_PERSIST, X.FLAG_NO_XCD_MAP, X.FLAG_NO_PERSIST | X.FLAG_NO_XCD_MAP):
+        got, _ = run(x, fmt, "i8", flags=flags)
+        np.testing.assert_array_equal(got, ref, err_msg="flags %#x" % flags)
+
+
 def test_no_xcd_map_gives_the_same_result():
     x = synth.random_input(20, 70, 256, "ci4", seed=3, device=DEV)
     a, _ = run(x, "ci4", "i8")
