@@ -41,24 +41,50 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_path(torch, xcorr, x, w, path, steps, warmup, flags=0):
-    """Average ms of one accumulate_dump window on the plan's stream (HIP events)."""
+def time_path(torch, xcorr, x, w, path, steps, warmup, flags=0, per_step=None):
+    """Average ms of one accumulate_dump window on the plan's stream (HIP
+    events around all steps).  If per_step is a list, the ms of each step
+    (events between steps) are appended to it."""
     p = xcorr.Plan(w.n_inputs, w.n_channels, w.fmt, path, flags=flags)
     out = p.new_output()
     for _ in range(warmup):
         p.accumulate_dump(x, out)
     torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(p.stream)
+    for k in range(steps):
+        p.accumulate_dump(x, out)
+        ev[k + 1].record(p.stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    if per_step is not None:
+        per_step.extend(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
+    info = p.query()
+    p.close()
+    return ms, out, info
+
+
+def time_accumulate(torch, xcorr, x, w, steps, warmup):
+    """Average ms of xcorr_accumulate alone (int64 plan: its accumulator is
+    read and written by every window)."""
+    p = xcorr.Plan(w.n_inputs, w.n_channels, w.fmt, "i8")
+    for _ in range(warmup):
+        p.accumulate(x)
+    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(p.stream)
     for _ in range(steps):
-        p.accumulate_dump(x, out)
+        p.accumulate(x)
     e1.record(p.stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    info = p.query()
     p.close()
-    return ms, out, info
+    return e0.elapsed_time(e1) / steps
+
+
+def percentile(v, q):
+    s = sorted(v)
+    return s[min(len(s) - 1, max(0, int(round(q / 100.0 * (len(s) - 1)))))]
 
 
 def kernel_sources_sha256() -> str:
@@ -327,7 +353,9 @@ def main():
     # has 4096), in the 8 bytes per baseline a complex float takes.  The
     # int64-output plan is timed right after it for comparison.
     log("int8 MFMA path, int32 output: %d warmup + %d timed windows" % (args.warmup, args.steps))
-    ms, out, info = time_path(torch, xcorr, x, w, "i8", args.steps, args.warmup, flags=xcorr.FLAG_OUT_I32)
+    steps_ms = []
+    ms, out, info = time_path(torch, xcorr, x, w, "i8", args.steps, args.warmup, flags=xcorr.FLAG_OUT_I32,
+                              per_step=steps_ms)
     cmac = w.cmac
     tcmac = cmac / (ms * 1e-3) / 1e12
     tops = 8 * cmac / (ms * 1e-3) / 1e12
@@ -344,6 +372,8 @@ def main():
     del out64
     tops64 = 8 * cmac / (ms64 * 1e-3) / 1e12
     log("int8, int64 out: %.3f ms/window, %.1f%% of int8 peak" % (ms64, 100 * tops64 / PEAK_INT8_TOPS))
+    ms_acc = time_accumulate(torch, xcorr, x, w, max(2, args.steps // 2), 1)
+    log("int8, accumulate only (int64 accumulator): %.3f ms/window" % ms_acc)
 
     result = {
         "metric": METRIC, "value": round(tcmac, 3), "unit": "TCMAC/s", "n_gpus": 1,
@@ -359,8 +389,13 @@ def main():
                    "path": "int8 MFMA, int32 partials, int32 (re, im) output, bit-exact (window <= 65535 samples)",
                    "entry_point": "xcorr_accumulate_dump(reset=1), plan flag XCORR_FLAG_OUT_I32",
                    "work_items": info.work_items},
+        "step_ms": {"p10": round(percentile(steps_ms, 10), 4), "p50": round(percentile(steps_ms, 50), 4),
+                    "p90": round(percentile(steps_ms, 90), 4)},
         "int64_output": {"ms_per_step": round(ms64, 4), "value": round(cmac / (ms64 * 1e-3) / 1e12, 3),
                          "pct_int8_peak": round(100 * tops64 / PEAK_INT8_TOPS, 2)},
+        "accumulate_only": {"ms_per_step": round(ms_acc, 4),
+                            "pct_int8_peak": round(100 * 8 * cmac / (ms_acc * 1e-3) / 1e12 / PEAK_INT8_TOPS, 2),
+                            "note": "xcorr_accumulate into the plan's int64 accumulator (read and written)"},
         "roofline": {"bound": "mfma",
                      "kernel": "xcorr_i8_persist_kernel<V_%s_DMA4, int32 out>" % w.fmt.upper(),
                      "achieved": round(tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
