@@ -289,6 +289,48 @@ def fstage_leg(torch, xcorr, w, reps=3, n_taps=2):
             "hbm_bytes": nbytes, "hbm_gbs": round(nbytes / ms / 1e6, 1)}
 
 
+def variants_leg(torch, xcorr, x, w, reps=3, period=700, on=0.09):
+    """Pulsar gating and baseline-dependent integration at the workload's
+    size: two gates (on-pulse for the first `on` of every `period` samples,
+    off-pulse the rest) through xcorr_accumulate_gated, and a tile dump of a
+    third of the 64 x 64 tiles with restart (bytes: the selected entries
+    read, written out and zeroed)."""
+    import numpy as np
+    g = np.array([1 if (t % period) < on * period else 0 for t in range(w.n_time)], dtype=np.uint8)
+    plans = [xcorr.Plan(w.n_inputs, w.n_channels, w.fmt, "i8") for _ in range(2)]
+    xcorr.accumulate_gated(plans, x, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        xcorr.accumulate_gated(plans, x, g)
+    torch.cuda.synchronize()
+    ms_gated = (time.perf_counter() - t0) * 1e3 / reps
+    p = plans[0]
+    out = p.new_output()
+    nr = (w.n_inputs + 63) // 64
+    sel = [1 if k % 3 == 0 else 0 for k in range(nr * (nr + 1) // 2)]
+    p.dump_tiles(out, sel, reset=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(p.stream)
+    for _ in range(reps):
+        p.dump_tiles(out, sel, reset=True)
+    e1.record(p.stream)
+    torch.cuda.synchronize()
+    ms_tiles = e0.elapsed_time(e1) / reps
+    frac = sum(sel) / len(sel)
+    for q in plans:
+        q.close()
+    del out
+    torch.cuda.empty_cache()
+    return {"gated": {"gates": 2, "period": period, "on_fraction": on, "ms": round(ms_gated, 3),
+                      "tcmac_s": round(w.cmac / ms_gated / 1e9, 1),
+                      "note": "host wall clock per call (the call waits for its stream once)"},
+            "tile_dump": {"tiles_selected": sum(sel), "tiles": len(sel), "ms": round(ms_tiles, 4),
+                          "gbs": round(3 * frac * w.output_bytes / ms_tiles / 1e6, 1)}}
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The oracle on a bounded sample of the same workload (host cores)."""
     import oracle
@@ -320,6 +362,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the fp16 / fp32 kernels")
     ap.add_argument("--no-corner-turn", action="store_true", help="skip the corner-turn leg")
     ap.add_argument("--no-fstage", action="store_true", help="skip the F-stage leg")
+    ap.add_argument("--no-variants", action="store_true", help="skip the gating / tile-dump leg")
     ap.add_argument("--workload", default="lwa",
                     help="synthetic workload of the timed window (default lwa, the headline; others for profiling)")
     ap.add_argument("--serving-seconds", type=float, default=4.0,
@@ -436,6 +479,11 @@ def main():
         log("corner turn at the same size")
         result["corner_turn"] = corner_turn_leg(torch, xcorr, w)
         log("corner turn:", result["corner_turn"])
+
+    if not args.no_variants and w.name == "lwa":
+        log("pulsar gating and tile dumps at the same size")
+        result["accumulate_variants"] = variants_leg(torch, xcorr, x, w)
+        log("accumulate variants:", result["accumulate_variants"])
 
     if not args.no_fstage and w.name == "lwa":
         log("F-stage making the same workload")
