@@ -103,6 +103,8 @@ def test_equalised_spectra_within_the_bound(n_in, n_spec, P, ch0, n_ch, extra):
     (20, 4, 2, 1000, 1628, 333),
     (3, 3, 1, 4000, 96, 8191),
     (48, 9, 2, 7, 9, 5),
+    (1, 2, 2, 4095, 1, 0),         # one input, the last channel only
+    (33, 40, 1, 0, 17, 7),         # runs of spectra across two workgroups per input
 ])
 def test_requantised_codes_match_the_oracle(n_in, n_spec, P, ch0, n_ch, extra):
     say("fstage ci4", n_in, n_spec, P, ch0, n_ch, extra)
