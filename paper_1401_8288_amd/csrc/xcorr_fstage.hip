@@ -118,7 +118,6 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
     __shared__ float2 L[kBuf];          // pass exchanges; then Z[k] at k + k / 16
     __shared__ float2 T1[16 * 256];     // [k0][t]  W4096^(t k0)
     __shared__ float2 T2[256];          // [k1][n0] W256^(n0 k1)
-    __shared__ float2 TB[16];           // W8192^j
 
     const int t = threadIdx.x;
     const int ai = blockIdx.x % a.n_inputs;
@@ -134,8 +133,23 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
 #pragma unroll
     for (int k0 = 0; k0 < 16; ++k0) T1[k0 * 256 + t] = twiddle((t * k0) & 4095, 4096);
     T2[t] = twiddle(((t & 15) * (t >> 4)) & 255, 256);
-    if (t < 16) TB[t] = twiddle(t, kN);
-    const float2 ta = twiddle(16 * t, kN);       // W8192^(16 t)
+    // W8192^k for this thread's channels k = 16 t + j: W^(16 t) times
+    // powers of W^1, multiplied out in double precision, then rounded
+    float2 wk[16];
+    {
+        double br, bi, sr, si;
+        sincospi(2.0 * (16 * t) / kN, &bi, &br);
+        sincospi(2.0 / kN, &si, &sr);
+        bi = -bi;
+        si = -si;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            wk[j] = make_float2((float)br, (float)bi);
+            const double nr = br * sr - bi * si, ni = br * si + bi * sr;
+            br = nr;
+            bi = ni;
+        }
+    }
 
     // prototype-filter coefficients of this thread's samples,
     // h[p N + 512 n2 + 2 t + e], and the input's gains for its channels
@@ -218,7 +232,7 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
                 // X = (s - i W8192^k d) / 2 with s = Z[k] + conj Z[-k] and
                 // d = Z[k] - conj Z[-k] (the even- and odd-sample transforms)
                 const float sx = zk.x + zc.x, sy = zk.y - zc.y, dx = zk.x - zc.x, dy = zk.y + zc.y;
-                const float2 w = cmul(ta, TB[j]);
+                const float2 w = wk[j];
                 const float vr = gh[j] * fmaf(w.x, dy, fmaf(w.y, dx, sx));
                 const float vi = gh[j] * fmaf(-w.x, dx, fmaf(w.y, dy, sy));
                 if constexpr (OUT == 0) {
