@@ -405,6 +405,15 @@ __device__ __forceinline__ void prepare(const Raw<FMT>& r, Ops& o)
             if (need_i<KIND>(b)) { o.ia[b] = r.o.ia[b]; o.ib[b] = r.o.ib[b]; }
             if (need_j<KIND>(b)) { o.ja[b] = r.o.ja[b]; o.jb[b] = r.o.jb[b]; }
         }
+        if constexpr (is_ci4(FMT) && is_dma(FMT)) {
+            // Keep the split in the step that read the fragments.  Without
+            // these opaque copies the compiler folds the split of a group's
+            // last step into the loop-carried value and redoes it at the top
+            // of the next group, where it doubles that step's vector work
+            // and holds back its first MFMAs (about 2 % of the launch).
+            if (need_i<KIND>(b)) { asm("" : "+v"(o.ia[b])); asm("" : "+v"(o.ib[b])); }
+            if (need_j<KIND>(b)) { asm("" : "+v"(o.ja[b])); asm("" : "+v"(o.jb[b])); }
+        }
         if (same_block<KIND>(0) && column_on(KIND, b)) {
             o.ja[b] = o.ia[b];
             o.jb[b] = o.ib[b];
