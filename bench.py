@@ -33,8 +33,11 @@ PEAK_HBM_GBS = 8000.0
 # HBM-traffic record of the int8 kernel (FETCH_SIZE / WRITE_SIZE counters on
 # this workload plus a copy-kernel calibration), tied to the kernel sources.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xcorr_i8_lwa_traffic.md")
+# The kernel, its launch arguments, the work-item plan (xcorr_api.cpp) and
+# the build flags: a change to any of them can change the kernel's traffic.
 KERNEL_SOURCES = ("paper_1401_8288_amd/csrc/xcorr_i8.hip", "paper_1401_8288_amd/csrc/xcorr_device.h",
-                  "paper_1401_8288_amd/csrc/xcorr_internal.h", "paper_1401_8288_amd/build.py")
+                  "paper_1401_8288_amd/csrc/xcorr_internal.h", "paper_1401_8288_amd/csrc/xcorr_api.cpp",
+                  "paper_1401_8288_amd/build.py")
 
 
 def log(*a):

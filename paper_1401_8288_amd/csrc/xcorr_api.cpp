@@ -69,13 +69,14 @@ LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_str
     a.n_inputs = p->d.n_inputs;
     a.t_len = t_len;
     a.n_channels = p->d.n_channels;
-    a.ch_group = p->ch_group;
-    a.n_items = p->n_items;
-    a.n_blocks = p->n_items * p->n_groups;
+    const bool add = src != nullptr;
+    a.ch_group = add ? p->ch_group_src : p->ch_group;
+    a.n_items = add ? p->n_items_src : p->n_items;
+    a.n_blocks = add ? p->n_items_src * p->n_groups_src : p->n_items * p->n_groups;
     a.xcd_map = p->xcd_map;
     a.out32 = p->out32;
     a.reserved = 0;
-    a.items = p->d_items;
+    a.items = add ? p->d_items_src : p->d_items;
     a.src = src;
     a.dst = dst;
     return a;
@@ -201,7 +202,7 @@ void plan_items4(int W, std::vector<WorkItem>& items, int& ch_group)
 // most 8 blocks per wave: every FULL tile becomes two HALF waves, a diagonal
 // tile two balanced DIAG_A / DIAG_B waves of 5 blocks, and the off-diagonal
 // tile inside a diagonal pair four QUART waves of 4 blocks, so a diagonal
-// work item costs 5/8 of an off-diagonal one.
+// work item issues 9/16 of the MFMAs of an off-diagonal one per SIMD.
 void plan_items8(int W, std::vector<WorkItem>& items, int& ch_group)
 {
     items.clear();
@@ -263,10 +264,115 @@ void plan_items8(int W, std::vector<WorkItem>& items, int& ch_group)
     }
 }
 
-void plan_items(int path, int tile, int W, std::vector<WorkItem>& items, int& ch_group)
+void plan_items8_paired(int W, std::vector<WorkItem>& items, int& ch_group)
 {
-    if (path == XCORR_PATH_I8_MFMA && tile != kTileW4) plan_items8(W, items, ch_group);
-    else plan_items4(W, items, ch_group);
+    items.clear();
+    // Two channels per group.  An off-diagonal pair of row-block pairs is
+    // one item per channel.  The diagonal pairs of both channels share one
+    // item: the full tile of each channel as two HALF waves (waves 0-3) and
+    // each diagonal tile as one DIAG wave of 10 blocks (waves 4-7), so that
+    // the item keeps every SIMD at 18 blocks instead of 9.  A step of an
+    // item costs about the same whatever its MFMA count (its copies,
+    // barrier and fragment reads do not shrink with it): a diagonal item of
+    // one channel, 9 blocks per SIMD, took as long as an off-diagonal one.
+    // Items run in list order on the workgroups of an XCD, so the list is
+    // channel-major: the off-diagonal items of the first channel, the
+    // shared diagonal items, then the off-diagonal items of the second
+    // channel; the workgroups running at one time then mostly read one
+    // channel.
+    ch_group = 2;
+    const int SB = (W + 1) / 2;
+    auto super_rows = [&](int R, int* r) {
+        int n = 0;
+        for (int k = 0; k < 2; ++k) if (2 * R + k < W) r[n++] = 2 * R + k;
+        return n;
+    };
+    auto off_items = [&](int c) {
+        for (int R = 0; R < SB; ++R) {
+            int rr[2], ss[2];
+            const int nr = super_rows(R, rr);
+            for (int S = 0; S < R; ++S) {
+                const int ns = super_rows(S, ss);
+                WorkItem it = blank_item();
+                int slot = 0;
+                for (int k = 0; k < nr; ++k) { it.ch[slot] = (int8_t)c; it.rb[slot++] = (int16_t)rr[k]; }
+                for (int k = 0; k < ns; ++k) { it.ch[slot] = (int8_t)c; it.rb[slot++] = (int16_t)ss[k]; }
+                int w = 0;
+                for (int a = 0; a < nr; ++a)
+                    for (int b = 0; b < ns; ++b)
+                        for (int h = 0; h < 2; ++h) {
+                            it.wi[w] = (int8_t)a;
+                            it.wj[w] = (int8_t)(nr + b);
+                            it.kind[w++] = h ? KIND_HALF1 : KIND_HALF0;
+                        }
+                items.push_back(it);
+            }
+        }
+    };
+    off_items(0);
+    for (int R = 0; R < SB; ++R) {
+        int rr[2];
+        const int nr = super_rows(R, rr);
+        WorkItem it = blank_item();
+        if (nr == 2) {
+            for (int c = 0; c < 2; ++c)
+                for (int k = 0; k < 2; ++k) {
+                    it.rb[2 * c + k] = (int16_t)rr[k];
+                    it.ch[2 * c + k] = (int8_t)c;
+                }
+            for (int c = 0; c < 2; ++c)
+                for (int h = 0; h < 2; ++h) {
+                    it.wi[2 * c + h] = (int8_t)(2 * c + 1);
+                    it.wj[2 * c + h] = (int8_t)(2 * c);
+                    it.kind[2 * c + h] = h ? KIND_HALF1 : KIND_HALF0;
+                }
+            for (int s = 0; s < 4; ++s) {
+                it.wi[4 + s] = it.wj[4 + s] = (int8_t)s;
+                it.kind[4 + s] = KIND_DIAG;
+            }
+        } else {
+            for (int c = 0; c < 2; ++c) {
+                it.rb[c] = (int16_t)rr[0];
+                it.ch[c] = (int8_t)c;
+                for (int h = 0; h < 2; ++h) {
+                    it.wi[2 * c + h] = it.wj[2 * c + h] = (int8_t)c;
+                    it.kind[2 * c + h] = h ? KIND_DIAG_B : KIND_DIAG_A;
+                }
+            }
+        }
+        items.push_back(it);
+    }
+    off_items(1);
+}
+
+// Work items of a plan: items / ch_group for launches that write their
+// result (reset, dump), items_src / cg_src for launches that add to an
+// accumulator.  4-bit int8 plans pair the diagonal items of two channels in
+// the first table only: pairing made adding launches 6 % slower at the LWA
+// size (their epilogue reads the accumulator, and the 10-block waves of the
+// shared items make it longer).  8-bit plans keep one channel per item in
+// both, because the paired list made the 2048-input 8-bit window 6 % slower
+// (twice the channels in flight per XCD for samples twice as wide).
+void plan_items(int path, int tile, int fmt, int W, std::vector<WorkItem>& items, int& ch_group,
+                std::vector<WorkItem>& items_src, int& cg_src)
+{
+    const bool i8 = path == XCORR_PATH_I8_MFMA && tile != kTileW4;
+    if (i8) plan_items8(W, items_src, cg_src);
+    else plan_items4(W, items_src, cg_src);
+    if (i8 && fmt == XCORR_CI4 && W > 1) {
+        plan_items8_paired(W, items, ch_group);
+    } else {
+        items = items_src;
+        ch_group = cg_src;
+    }
+}
+
+// Items the plan's device table holds: one list, or both when they differ.
+size_t stored_items(const std::vector<WorkItem>& items, int cg, const std::vector<WorkItem>& items_src, int cg_src)
+{
+    const bool same = cg == cg_src && items.size() == items_src.size() &&
+                      std::memcmp(items.data(), items_src.data(), items.size() * sizeof(WorkItem)) == 0;
+    return same ? items.size() : items.size() + items_src.size();
 }
 
 // The four-wave int8 kernel as a one-entry persistent launch.
@@ -413,10 +519,11 @@ xcorr_status xcorr_plan_bytes(const xcorr_plan_desc* d, size_t* bytes)
     xcorr_status s = check_desc(d);
     if (s != XCORR_OK) return s;
     if (!bytes) return fail(XCORR_ERR_ARG, "null output");
-    std::vector<WorkItem> items;
-    int cg;
-    plan_items(d->path, d->tile, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, cg);
-    *bytes = plan_device_bytes(d, items.size());
+    std::vector<WorkItem> items, items_src;
+    int cg, cg_src;
+    plan_items(d->path, d->tile, d->format, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, cg, items_src,
+               cg_src);
+    *bytes = plan_device_bytes(d, stored_items(items, cg, items_src, cg_src));
     return XCORR_OK;
 }
 
@@ -451,17 +558,21 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
 
     p->tile = d->tile;
     std::vector<WorkItem>& items = p->h_items;
-    plan_items(d->path, d->tile, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, p->ch_group);
+    plan_items(d->path, d->tile, d->format, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, p->ch_group,
+               p->h_items_src, p->ch_group_src);
     p->n_items = (int)items.size();
     p->n_groups = (d->n_channels + p->ch_group - 1) / p->ch_group;
-    const int64_t blocks = (int64_t)p->n_items * p->n_groups;
+    p->n_items_src = (int)p->h_items_src.size();
+    p->n_groups_src = (d->n_channels + p->ch_group_src - 1) / p->ch_group_src;
+    p->n_items_stored = stored_items(items, p->ch_group, p->h_items_src, p->ch_group_src);
+    const int64_t blocks = std::max((int64_t)p->n_items * p->n_groups, (int64_t)p->n_items_src * p->n_groups_src);
     if (blocks > (int64_t)1 << 30) {
         delete p;
         return fail(XCORR_ERR_UNSUPPORTED, "too many work items");
     }
 
     e = hipMalloc(&p->acc, p->out_bytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, items.size() * sizeof(WorkItem));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, p->n_items_stored * sizeof(WorkItem));
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_counters, 8 * sizeof(int));
     if (e != hipSuccess) {
         release(p->acc);
@@ -473,6 +584,12 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
                     "plan allocation: %s", hipGetErrorString(e));
     }
     e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    p->d_items_src = p->d_items;
+    if (e == hipSuccess && p->n_items_stored > items.size()) {
+        p->d_items_src = p->d_items + items.size();
+        e = hipMemcpy(p->d_items_src, p->h_items_src.data(), p->h_items_src.size() * sizeof(WorkItem),
+                      hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         release(p->acc);
         release(p->d_items);
@@ -558,7 +675,7 @@ xcorr_status xcorr_query(xcorr_plan_t p, xcorr_plan_info* info)
 {
     if (!live(p)) return fail(XCORR_ERR_STATE, "invalid plan handle");
     if (!info) return fail(XCORR_ERR_ARG, "null info");
-    info->device_bytes = plan_device_bytes(&p->d, p->n_items);
+    info->device_bytes = plan_device_bytes(&p->d, p->n_items_stored);
     info->output_bytes = p->out_bytes;
     info->input_bytes_per_sample =
         (size_t)p->d.n_inputs * (p->d.format == XCORR_CI4 ? 1 : 2) * p->d.n_channels;

@@ -72,11 +72,14 @@ void make_slices(const std::vector<Entry>& es, const int* first, int n_blocks, i
     double total = 0;
     for (size_t e = 0; e < es.size(); ++e) {
         const xcorr_plan_s* p = es[e].plan;
+        const bool add = es[e].a.items != p->d_items;          // the table of adding launches
+        const std::vector<WorkItem>& its = add ? p->h_items_src : p->h_items;
+        const int n_items = es[e].a.n_items;
         double gc = 0;
-        for (const WorkItem& it : p->h_items) gc += item_blocks(it);
+        for (const WorkItem& it : its) gc += item_blocks(it);
         gc *= (double)es[e].t_len;
-        for (int g = 0; g < p->n_groups; ++g) {
-            groups.emplace_back(first[e] + g * p->n_items, gc);
+        for (int g = 0; g < es[e].a.n_blocks / n_items; ++g) {
+            groups.emplace_back(first[e] + g * n_items, gc);
             total += gc;
         }
     }

@@ -20,6 +20,15 @@ struct xcorr_plan_s {
     int n_items = 0;                // items per channel group
     int ch_group = 1;
     int n_groups = 0;
+    // Launches that add to an accumulator (src != null) use a second table:
+    // one channel per item, since the paired diagonal items of 4-bit plans
+    // make those launches slower.  Equal to the first when nothing is paired.
+    xcorr::WorkItem* d_items_src = nullptr;   // inside the d_items allocation
+    std::vector<xcorr::WorkItem> h_items_src;
+    int n_items_src = 0;
+    int ch_group_src = 1;
+    int n_groups_src = 0;
+    size_t n_items_stored = 0;      // items in the d_items allocation
     int xcd_map = 1;
     int out32 = 0;                  // int32 (re, im) output (XCORR_FLAG_OUT_I32)
     int tile = 0;                   // int8 tile variant in use

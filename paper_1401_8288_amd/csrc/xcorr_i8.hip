@@ -785,6 +785,7 @@ __device__ __forceinline__ void dispatch_kind(const LaunchArgs& a, const WaveJob
     case KIND_HALF1:  run_tile<FMT, KIND_HALF1, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
     case KIND_DIAG_A: run_tile<FMT, KIND_DIAG_A, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
     case KIND_DIAG_B: run_tile<FMT, KIND_DIAG_B, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_DIAG:   run_tile<FMT, KIND_DIAG, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
     case KIND_QUART0: run_tile<FMT, KIND_QUART0, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
     case KIND_QUART1: run_tile<FMT, KIND_QUART1, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
     case KIND_QUART2: run_tile<FMT, KIND_QUART2, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;

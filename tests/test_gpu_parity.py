@@ -385,3 +385,25 @@ def test_many_inputs_one_channel(fmt):
     np.testing.assert_array_equal(got, ref)
     got32, _ = run(x, fmt, "i8", flags=xc().FLAG_OUT_I32)
     np.testing.assert_array_equal(got32.astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("tile", [0, 1, 3])
+@pytest.mark.parametrize("shape", [(128, 1, 200), (192, 3, 129), (320, 5, 64), (256, 2, 300), (448, 7, 70),
+                                   (100, 3, 90)], ids=lambda s: "x".join(map(str, s)))
+def test_4bit_items_pair_diagonals_of_two_channels(tile, shape):
+    # 4-bit plans put the diagonal tiles of two channels into one work item;
+    # odd channel counts leave the second channel of the last group empty,
+    # odd row-block counts end with a single-block diagonal item
+    n_in, n_ch, n_t = shape
+    if tile == 1 and n_in % 16:
+        pytest.skip("the LDS-DMA tiles need n_inputs % 16 == 0")
+    say("paired diagonal items", shape, "tile", tile)
+    x = synth.random_input(n_ch, n_t, n_in, "ci4", seed=n_in + n_ch, device=DEV)
+    ref = oracle.correlate(x.cpu().numpy(), "ci4")
+    p = xc().Plan(n_in, n_ch, "ci4", "i8", tile=tile)
+    assert p.query().channels_per_group == 2
+    p.close()
+    got, _ = run(x, "ci4", "i8", tile=tile)
+    np.testing.assert_array_equal(got, ref)
+    got32, _ = run(x, "ci4", "i8", tile=tile, flags=xc().FLAG_OUT_I32)
+    np.testing.assert_array_equal(got32.astype(np.int64), ref)
