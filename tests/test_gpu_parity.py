@@ -407,3 +407,38 @@ def test_4bit_items_pair_diagonals_of_two_channels(tile, shape):
     np.testing.assert_array_equal(got, ref)
     got32, _ = run(x, "ci4", "i8", tile=tile, flags=xc().FLAG_OUT_I32)
     np.testing.assert_array_equal(got32.astype(np.int64), ref)
+    # launches that add to the accumulator take the single-channel items,
+    # launches that write their result the paired ones: mix both in a window
+    k = n_t // 3
+    p = xc().Plan(n_in, n_ch, "ci4", "i8", tile=tile)
+    p.accumulate(x[:, :k].contiguous())
+    p.accumulate(x[:, k:2 * k].contiguous())
+    out, info = p.accumulate_dump(x[:, 2 * k:].contiguous())
+    torch.cuda.synchronize()
+    assert info.samples_accumulated == n_t
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+    out, _ = p.accumulate_dump(x)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+    p.close()
+
+
+@pytest.mark.parametrize("n_in,n_ch,n_t", [(16, 40, 70000), (32, 33, 300), (64, 128, 129)])
+def test_8bit_plane_split_runs_beside_the_kernel(n_in, n_ch, n_t):
+    # with 32 channels or more the 8-bit LDS-DMA path splits each chunk into
+    # channel groups whose re | im plane split runs on a side stream ahead
+    # of the kernel; 70000 samples make two chunks (fold bound 65535), the
+    # second adding to the first; 33 channels give uneven groups
+    say("8-bit plane split beside the kernel", n_in, n_ch, n_t)
+    x = synth.random_input(n_ch, n_t, n_in, "ci8", seed=n_ch, device=DEV)
+    ref = oracle.correlate(x.cpu().numpy(), "ci8")
+    got, info = run(x, "ci8", "i8")
+    assert info.samples_accumulated == n_t
+    np.testing.assert_array_equal(got, ref)
+    p = xc().Plan(n_in, n_ch, "ci8", "i8")
+    k = n_t // 2
+    p.accumulate(x[:, :k].contiguous())
+    out, _ = p.accumulate_dump(x[:, k:].contiguous())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+    p.close()
