@@ -83,7 +83,12 @@ typedef enum {
  * pass into a staging buffer the plan holds and grows to its largest chunk,
  * which xcorr_plan_bytes does not count).  Growing it waits for the plan's
  * stream and allocates, so a call that would grow it cannot run under
- * stream capture; one window of the largest size first avoids that.
+ * stream capture; one window of the largest size first avoids that.  With
+ * 32 channels or more (4 per group of 8) the split of each channel group
+ * runs on a second stream the plan creates on first use (with its events),
+ * ordered after the work already on the plan's stream, and the kernel of
+ * each group waits on the plan's stream for that group's split; the
+ * calls return with all their work ordered on the plan's stream, as usual.
  * Batches of 8-bit plans use the register tile.  DMA8 and W4 take 4-bit
  * samples only. */
 #define XCORR_TILE_DEFAULT 0       /* LDS-DMA depth 4 where allowed, else registers */
