@@ -30,13 +30,15 @@ PEAK_INT8_TOPS = 5000.0       # MI355X dense int8 MFMA, vendor figure
 PEAK_FP16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_CLOCK_MHZ = 2400.0       # shader clock at which the vendor peaks are quoted
+CLOCK_PROBE_MS = 20.0         # wall time the clock probe spans during timed windows
 # HBM-traffic record of the int8 kernel (FETCH_SIZE / WRITE_SIZE counters on
 # this workload plus a copy-kernel calibration), tied to the kernel sources.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xcorr_i8_lwa_traffic.md")
-# The kernel, its launch arguments, the work-item plan (xcorr_api.cpp) and
+# The kernel, its launch arguments, the work-item plan (xcorr_items.cpp) and
 # the build flags: a change to any of them can change the kernel's traffic.
 KERNEL_SOURCES = ("paper_1401_8288_amd/csrc/xcorr_i8.hip", "paper_1401_8288_amd/csrc/xcorr_device.h",
-                  "paper_1401_8288_amd/csrc/xcorr_internal.h", "paper_1401_8288_amd/csrc/xcorr_api.cpp",
+                  "paper_1401_8288_amd/csrc/xcorr_internal.h", "paper_1401_8288_amd/csrc/xcorr_items.cpp",
                   "paper_1401_8288_amd/build.py")
 
 
@@ -44,10 +46,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_path(torch, xcorr, x, w, path, steps, warmup, flags=0, per_step=None):
+def time_path(torch, xcorr, x, w, path, steps, warmup, flags=0, per_step=None, clock=None):
     """Average ms of one accumulate_dump window on the plan's stream (HIP
     events around all steps).  If per_step is a list, the ms of each step
-    (events between steps) are appended to it."""
+    (events between steps) are appended to it.  If clock is a dict, after
+    the timed steps a few more windows run untimed with a clock probe on a
+    side stream beside them, and clock["mhz"] receives the shader clock it
+    saw (the probe is kept out of the timed steps: its wave shares a CU with
+    one workgroup of the persistent launch)."""
     p = xcorr.Plan(w.n_inputs, w.n_channels, w.fmt, path, flags=flags)
     out = p.new_output()
     for _ in range(warmup):
@@ -60,6 +66,15 @@ def time_path(torch, xcorr, x, w, path, steps, warmup, flags=0, per_step=None):
         ev[k + 1].record(p.stream)
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[steps]) / steps
+    if clock is not None:
+        probe = xcorr.ClockProbe(x.device)
+        side = torch.cuda.Stream(device=x.device)
+        n_extra = max(2, int(2 * CLOCK_PROBE_MS / ms) + 1)
+        for _ in range(n_extra):
+            p.accumulate_dump(x, out)
+        probe.start(CLOCK_PROBE_MS, side)       # enqueued after the windows: starts beside the first
+        torch.cuda.synchronize()
+        clock["mhz"] = probe.mhz()
     if per_step is not None:
         per_step.extend(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
     info = p.query()
@@ -400,8 +415,9 @@ def main():
     # int64-output plan is timed right after it for comparison.
     log("int8 MFMA path, int32 output: %d warmup + %d timed windows" % (args.warmup, args.steps))
     steps_ms = []
+    clock = {}
     ms, out, info = time_path(torch, xcorr, x, w, "i8", args.steps, args.warmup, flags=xcorr.FLAG_OUT_I32,
-                              per_step=steps_ms)
+                              per_step=steps_ms, clock=clock)
     cmac = w.cmac
     tcmac = cmac / (ms * 1e-3) / 1e12
     tops = 8 * cmac / (ms * 1e-3) / 1e12
@@ -451,6 +467,14 @@ def main():
                      "hbm_gbs_algorithmic": round(hbm_bytes / (ms * 1e-3) / 1e9, 1)},
         "pct_int8_peak": round(100 * tops / PEAK_INT8_TOPS, 2),
     }
+    if "mhz" in clock:
+        # the int8 peak scales with the shader clock (8192 ops per CU per cycle)
+        peak_now = PEAK_INT8_TOPS * clock["mhz"] / PEAK_CLOCK_MHZ
+        result["roofline"]["measured_clock_mhz"] = round(clock["mhz"], 1)
+        result["roofline"]["peak_at_measured_clock"] = round(peak_now, 1)
+        result["roofline"]["frac_at_measured_clock"] = round(tops / peak_now, 4)
+        log("shader clock during the timed windows: %.0f MHz; %.1f%% of the int8 peak at that clock"
+            % (clock["mhz"], 100 * tops / peak_now))
     traffic, how = read_traffic() if w.name == "lwa" else (None, "counters recorded for the lwa workload only")
     result["roofline"]["traffic"] = traffic
     result["roofline"]["traffic_source"] = how

@@ -262,6 +262,24 @@ xcorr_status xcorr_fstage(const xcorr_fstage_desc* desc, const void* d_adc, int6
 xcorr_status xcorr_fstage_work_bytes(const xcorr_fstage_desc* desc, int64_t n_samples, size_t* bytes);
 
 /* ------------------------------------------------------------------------
+ * Measurement support (not part of the method): the shader clock a kernel
+ * runs at, which sets the MFMA peak it can reach (the int8 peak is 8192
+ * ops per CU per cycle, so 5.03 POP/s at the 2.4 GHz peak clock of 256 CUs).
+ * ------------------------------------------------------------------------ */
+
+/* Launch one wave on `stream` (a hipStream_t, NULL = default stream) that
+ * waits `ticks` ticks of the constant-rate wall clock (at most 2^22 polls,
+ * so it always ends) and writes d_out[0..3] = wall-clock ticks at start and
+ * end, shader cycles at start and end (uint64, device memory, 8-byte
+ * aligned, caller-owned).  Launched on another stream beside a long kernel,
+ * (d_out[3] - d_out[2]) / (d_out[1] - d_out[0]) * wall_khz is the shader
+ * clock in kHz under that kernel's load.  *wall_khz receives the wall-clock
+ * rate (host pointer; may be NULL).  Errors: XCORR_ERR_ARG for a null or
+ * misaligned d_out or ticks outside [1, 2^32); XCORR_ERR_DEVICE if the
+ * launch fails.  Nothing is enqueued on error. */
+xcorr_status xcorr_clock_probe(void* d_out, int64_t ticks, int32_t* wall_khz, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batches: several plans (subarrays of uneven input and channel counts, the
  * X-stage of several arrays sharing one GPU, Sec. 3) run as ONE persistent
  * launch per time chunk.  Every plan of a batch must use XCORR_PATH_I8_MFMA

@@ -78,6 +78,13 @@ xcorr_status run_window_strided(xcorr_plan_s* p, const uint8_t* in, int64_t chan
                                 void* final_dst);
 // Relative cost of a work item (MFMA blocks its waves own).
 int item_blocks(const WorkItem& it);
+// Work items of a plan (xcorr_items.cpp): items / ch_group for launches that
+// write their result, items_src / cg_src for launches that add to an
+// accumulator; W row blocks of 64 inputs.
+void plan_items(int path, int tile, int fmt, int W, std::vector<WorkItem>& items, int& ch_group,
+                std::vector<WorkItem>& items_src, int& cg_src);
+// Items a plan's device table holds for those two lists.
+size_t stored_items(const std::vector<WorkItem>& items, int cg, const std::vector<WorkItem>& items_src, int cg_src);
 // One fused window (accumulate + dump with reset) for each plan, all in one
 // persistent launch per time chunk.  The plans must share the format.
 xcorr_status run_fused_windows(hipStream_t stream, int* d_counters, const xcorr_batch_config& cfg,

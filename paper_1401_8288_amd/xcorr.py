@@ -36,7 +36,7 @@ EXPORTS = ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dum
            "xcorr_server_create", "xcorr_server_open", "xcorr_server_submit", "xcorr_server_poll",
            "xcorr_server_wait", "xcorr_server_close", "xcorr_server_query", "xcorr_server_destroy",
            "xcorr_corner_turn", "xcorr_dump_tiles", "xcorr_accumulate_gated", "xcorr_fstage",
-           "xcorr_fstage_work_bytes")
+           "xcorr_fstage_work_bytes", "xcorr_clock_probe")
 
 
 class PlanDesc(ctypes.Structure):
@@ -142,6 +142,7 @@ def _load():
     L.xcorr_accumulate_gated.argtypes = [P(vp), i32, vp, i64, vp]
     L.xcorr_fstage.argtypes = [P(FstageDesc), vp, i64, i64, vp, vp, vp, vp, P(i64), vp]
     L.xcorr_fstage_work_bytes.argtypes = [P(FstageDesc), i64, P(ctypes.c_size_t)]
+    L.xcorr_clock_probe.argtypes = [vp, i64, P(ctypes.c_int32), vp]
     for name in EXPORTS:
         if name not in ("xcorr_strerror", "xcorr_last_error", "xcorr_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -602,3 +603,30 @@ def fstage(adc: torch.Tensor, coeff: torch.Tensor, gain: torch.Tensor, chan_begi
     if got.value != n_spec:
         raise RuntimeError("spectra count mismatch")
     return out
+
+
+class ClockProbe:
+    """Shader clock under load (measurement support): start() launches one
+    wave on `stream` that waits `ms` of wall-clock time; mhz(), once the
+    stream has passed it, is the shader clock that wave saw."""
+
+    def __init__(self, device=None):
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.buf = torch.zeros(4, dtype=torch.int64, device=dev)
+        khz = ctypes.c_int32(0)
+        # a one-tick probe, only to read the wall-clock rate
+        _check(lib.xcorr_clock_probe(ctypes.c_void_p(self.buf.data_ptr()), 1, ctypes.byref(khz),
+                                     ctypes.c_void_p(int(torch.cuda.current_stream(dev).cuda_stream))))
+        torch.cuda.synchronize(dev)
+        self.wall_khz = khz.value
+
+    def start(self, ms: float, stream: torch.cuda.Stream):
+        ticks = max(1, int(ms * self.wall_khz))
+        _check(lib.xcorr_clock_probe(ctypes.c_void_p(self.buf.data_ptr()), ticks, None,
+                                     ctypes.c_void_p(int(stream.cuda_stream))))
+
+    def mhz(self) -> float:
+        r0, r1, c0, c1 = (int(v) for v in self.buf.cpu())
+        if r1 <= r0 or self.wall_khz <= 0:
+            raise RuntimeError("clock probe did not run")
+        return (c1 - c0) / (r1 - r0) * self.wall_khz / 1e3

@@ -219,3 +219,13 @@ def test_int32_output_flag_checks():
         with pytest.raises(xcorr.XcorrError) as e:
             xcorr.plan_bytes(512, 64, "ci4", path, flags=xcorr.FLAG_OUT_I32, tile=tile)
         assert e.value.status == -6
+
+
+def test_clock_probe_argument_checks():
+    from paper_1401_8288_amd import xcorr
+    L = xcorr.lib
+    khz = ctypes.c_int32(0)
+    assert L.xcorr_clock_probe(None, 100, ctypes.byref(khz), None) == -1
+    assert L.xcorr_clock_probe(ctypes.c_void_p(0x1004), 100, None, None) == -1     # misaligned
+    assert L.xcorr_clock_probe(ctypes.c_void_p(0x1000), 0, None, None) == -1
+    assert L.xcorr_clock_probe(ctypes.c_void_p(0x1000), 1 << 32, None, None) == -1

@@ -442,3 +442,19 @@ def test_8bit_plane_split_runs_beside_the_kernel(n_in, n_ch, n_t):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), ref)
     p.close()
+
+
+def test_clock_probe_reports_a_plausible_shader_clock():
+    # measurement support: one wave waits 2 ms of wall-clock time; the
+    # shader clock it reports lies within what the chip can run at
+    X = xc()
+    probe = X.ClockProbe(DEV)
+    assert probe.wall_khz > 0
+    s = torch.cuda.Stream(device=DEV)
+    probe.start(2.0, s)
+    torch.cuda.synchronize()
+    r0, r1, c0, c1 = (int(v) for v in probe.buf.cpu())
+    assert (r1 - r0) >= 2.0 * probe.wall_khz
+    mhz = probe.mhz()
+    say("shader clock %.0f MHz (wall clock %d kHz)" % (mhz, probe.wall_khz))
+    assert 100.0 < mhz < 3000.0
