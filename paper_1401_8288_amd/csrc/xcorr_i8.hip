@@ -30,6 +30,7 @@
 // per sample and term pair); the host splits longer windows.
 #include "xcorr_device.h"
 
+#include <type_traits>
 #include <utility>
 
 namespace xcorr {
@@ -429,6 +430,15 @@ __device__ __forceinline__ constexpr int n_frags()
     return n;
 }
 
+// The block of a kind after block n (n = 4 * bi + bj), -1 after the last.
+template <int KIND>
+__device__ __forceinline__ constexpr int next_block(int n)
+{
+    for (int m = n + 1; m < 16; ++m)
+        if (block_on(KIND, m >> 2, m & 3)) return m;
+    return -1;
+}
+
 template <int KIND>
 __device__ __forceinline__ constexpr int n_blocks()
 {
@@ -715,43 +725,74 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
     const int i0 = w.rb_i * kRowBlock, j0 = w.rb_j * kRowBlock;
     const int shift = is_ci4(FMT) ? 8 : 0;
     const int64_t nb = (int64_t)a.n_inputs * (a.n_inputs + 1) / 2;
-    const int64_t* src = (const int64_t*)a.src;
-    int64_t* dst = (int64_t*)a.dst;
+    // Launches that add to a result (src, the plan's accumulator or the
+    // previous chunk's output) read it here.  src may be dst, so the
+    // compiler cannot move a load above an earlier store: the four loads of
+    // a block are written before its stores and, in the LDS-DMA variants,
+    // before the stores of the block ahead of it, so the wave waits for one
+    // memory round trip per item (per block in the register-staged
+    // variants, which have no registers to spare) instead of one per row.
+    typedef typename std::conditional<O32 != 0, int2, longlong2>::type Pair;
+    const Pair* src = (const Pair*)a.src;
+    Pair* dst = (Pair*)a.dst;
+    const int jl = lane & 15, il = 4 * (lane >> 4);
+    auto pair_index = [&](int n, int r, bool& ok) -> int64_t {
+        const int i = i0 + 16 * (n >> 2) + il + r, j = j0 + 16 * (n & 3) + jl;
+        ok = i < a.n_inputs && j <= i;
+        return (int64_t)ch * nb + (int64_t)i * (i + 1) / 2 + j;
+    };
+    auto load_block = [&](int n, Pair (&v)[4]) {
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+        for (int r = 0; r < 4; ++r) {
+            bool ok;
+            const int64_t q = pair_index(n, r, ok);
+            v[r].x = 0;
+            v[r].y = 0;
+            if (ok) v[r] = src[q];
+        }
+    };
+    if (!src) {
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-            if (!block_on(KIND, bi, bj)) continue;
-            const int j = j0 + 16 * bj + (lane & 15);
+        for (int n = 0; n < 16; ++n) {
+            if (!block_on(KIND, n >> 2, n & 3)) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = i0 + 16 * bi + 4 * (lane >> 4) + r;
-                if (i >= a.n_inputs || j > i) continue;
-                int64_t re = ((int64_t)c.re[bi][bj][r]) >> shift;
-                int64_t im = ((int64_t)c.ba[bi][bj][r] - (int64_t)c.ab[bi][bj][r]) >> shift;
-                const int64_t idx = ((int64_t)ch * nb + (int64_t)i * (i + 1) / 2 + j) * 2;
-                if constexpr (O32 != 0) {
-                    // int32 results: exact within the window bound the host enforces
-                    int2 o = make_int2((int)re, (int)im);
-                    if (src) {
-                        const int2 s = *((const int2*)src + idx / 2);
-                        o.x += s.x;
-                        o.y += s.y;
-                    }
-                    *((int2*)dst + idx / 2) = o;
-                    continue;
-                }
-                if (src) {
-                    const longlong2 s = *(const longlong2*)(src + idx);
-                    re += s.x;
-                    im += s.y;
-                }
-                longlong2 o;
-                o.x = re;
-                o.y = im;
-                *(longlong2*)(dst + idx) = o;
+                bool ok;
+                const int64_t q = pair_index(n, r, ok);
+                if (!ok) continue;
+                Pair o;
+                o.x = ((int64_t)c.re[n >> 2][n & 3][r]) >> shift;
+                o.y = ((int64_t)c.ba[n >> 2][n & 3][r] - (int64_t)c.ab[n >> 2][n & 3][r]) >> shift;
+                dst[q] = o;
             }
         }
+        return;
+    }
+    Pair cur[4], nxt[4];
+    constexpr bool ahead = is_dma(FMT);
+    if (ahead) load_block(next_block<KIND>(-1), nxt);
+#pragma unroll
+    for (int n = 0; n < 16; ++n) {
+        if (!block_on(KIND, n >> 2, n & 3)) continue;
+        if (ahead) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cur[r] = nxt[r];
+            if (next_block<KIND>(n) >= 0) load_block(next_block<KIND>(n), nxt);
+        } else {
+            load_block(n, cur);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            bool ok;
+            const int64_t q = pair_index(n, r, ok);
+            if (!ok) continue;
+            // int32 results are exact within the window bound the host enforces
+            Pair o;
+            o.x = (((int64_t)c.re[n >> 2][n & 3][r]) >> shift) + (int64_t)cur[r].x;
+            o.y = (((int64_t)c.ba[n >> 2][n & 3][r] - (int64_t)c.ab[n >> 2][n & 3][r]) >> shift) + (int64_t)cur[r].y;
+            dst[q] = o;
+        }
+    }
 }
 
 // The LDS buffers of a variant (kernel-lifetime LDS variables).
