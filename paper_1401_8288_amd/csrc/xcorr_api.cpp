@@ -259,7 +259,7 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
                                            (uint8_t*)dst + c0 * out_ch);
                 ag.n_channels = nc;
                 ag.n_blocks = ag.n_items * ((nc + ag.ch_group - 1) / ag.ch_group);
-                e = launch_i8(ag, p->d.format, p->tile, p->persist_grid, p->stream);
+                e = launch_i8(ag, p->d.format, p->tile, p->persist_grid, p->d_counters, p->stream);
                 if (e != hipSuccess) return hip_fail(e, "X-stage kernel launch");
             }
             return XCORR_OK;
@@ -268,7 +268,7 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
     switch (p->d.path) {
     case XCORR_PATH_I8_MFMA:
         e = p->tile == kTileW4 ? launch_w4(a, p->persist_grid ? p->persist_grid : 256, p->stream)
-                               : launch_i8(a, p->d.format, p->tile, p->persist_grid, p->stream);
+                               : launch_i8(a, p->d.format, p->tile, p->persist_grid, p->d_counters, p->stream);
         break;
     case XCORR_PATH_F16_MFMA: e = launch_f16(a, p->d.format, p->stream); break;
     default: e = launch_f32(a, p->d.format, p->stream); break;

@@ -633,14 +633,13 @@ __device__ __forceinline__ void pipeline_group(int k0, Stager<FMT>& st, const Bu
     (pipeline_step<FMT, KIND, S>(k0 + S, st, L, si, sj, lane, fo, ops, c), ...);
 }
 
-// One work item.  st stages this item's samples.  For the LDS-DMA variants a
-// persistent workgroup passes the stager of its next item (has_next, nst): its
-// first steps are copied before this item's epilogue, and the next item then
-// starts with issue_prologue = false.
-template <int FMT, int KIND, int O32>
+// One work item.  st stages this item's samples.  After the item's steps
+// (LDS-DMA variants) next(L) runs on every wave: a persistent workgroup
+// learns its next item there and copies its first steps before this item's
+// epilogue; the next item then starts with issue_prologue = false.
+template <int FMT, int KIND, int O32, class Next>
 __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane,
-                                         const Bufs& L, Stager<FMT>& st, bool has_next, const Stager<FMT>& nst,
-                                         bool issue_prologue)
+                                         const Bufs& L, Stager<FMT>& st, Next& next, bool issue_prologue)
 {
     uint8_t* lds = L.p[0];
     const int nk = (a.t_len + kStep - 1) / kStep;
@@ -711,10 +710,7 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
         // its last fragment reads, so a persistent workgroup can now copy its
         // next item's first steps, which then overlap this item's epilogue.
         wait_vm_lgkm<0>();
-        if (has_next) {
-#pragma unroll
-            for (int s = 0; s < dma_depth(FMT); ++s) nst.load(L.p[s], s);
-        }
+        next(L);
     }
     if (KIND == KIND_NONE) return;
 
@@ -816,24 +812,28 @@ __device__ __forceinline__ Bufs lds_buffers()
 
 // One work item (local index b of the launch arguments a) by the whole
 // workgroup.
-template <int FMT, int O32>
+template <int FMT, int O32, class Next>
 __device__ __forceinline__ void dispatch_kind(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane,
-                                              const Bufs& L, Stager<FMT>& st, bool has_next,
-                                              const Stager<FMT>& nst, bool issue_prologue)
+                                              const Bufs& L, Stager<FMT>& st, Next& next, bool issue_prologue)
 {
     switch (w.kind) {
-    case KIND_HALF0:  run_tile<FMT, KIND_HALF0, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_HALF1:  run_tile<FMT, KIND_HALF1, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_DIAG_A: run_tile<FMT, KIND_DIAG_A, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_DIAG_B: run_tile<FMT, KIND_DIAG_B, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_DIAG:   run_tile<FMT, KIND_DIAG, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_QUART0: run_tile<FMT, KIND_QUART0, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_QUART1: run_tile<FMT, KIND_QUART1, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_QUART2: run_tile<FMT, KIND_QUART2, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    case KIND_QUART3: run_tile<FMT, KIND_QUART3, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
-    default:          run_tile<FMT, KIND_NONE, O32>(a, w, lane, L, st, has_next, nst, issue_prologue); break;
+    case KIND_HALF0:  run_tile<FMT, KIND_HALF0, O32>(a, w, lane, L, st, next, issue_prologue); break;
+    case KIND_HALF1:  run_tile<FMT, KIND_HALF1, O32>(a, w, lane, L, st, next, issue_prologue); break;
+    case KIND_DIAG_A: run_tile<FMT, KIND_DIAG_A, O32>(a, w, lane, L, st, next, issue_prologue); break;
+    case KIND_DIAG_B: run_tile<FMT, KIND_DIAG_B, O32>(a, w, lane, L, st, next, issue_prologue); break;
+    case KIND_DIAG:   run_tile<FMT, KIND_DIAG, O32>(a, w, lane, L, st, next, issue_prologue); break;
+    case KIND_QUART0: run_tile<FMT, KIND_QUART0, O32>(a, w, lane, L, st, next, issue_prologue); break;
+    case KIND_QUART1: run_tile<FMT, KIND_QUART1, O32>(a, w, lane, L, st, next, issue_prologue); break;
+    case KIND_QUART2: run_tile<FMT, KIND_QUART2, O32>(a, w, lane, L, st, next, issue_prologue); break;
+    case KIND_QUART3: run_tile<FMT, KIND_QUART3, O32>(a, w, lane, L, st, next, issue_prologue); break;
+    default:          run_tile<FMT, KIND_NONE, O32>(a, w, lane, L, st, next, issue_prologue); break;
     }
 }
+
+// A workgroup that runs one item only.
+struct NoNext {
+    __device__ __forceinline__ void operator()(const Bufs&) {}
+};
 
 template <int FMT, int O32>
 __device__ __forceinline__ void process_item(const LaunchArgs& a, int b, const Bufs& L)
@@ -842,7 +842,8 @@ __device__ __forceinline__ void process_item(const LaunchArgs& a, int b, const B
     const int lane = threadIdx.x & 63;
     Stager<FMT> st;
     st.init(a, w, lane);
-    dispatch_kind<FMT, O32>(a, w, lane, L, st, false, st, true);
+    NoNext none;
+    dispatch_kind<FMT, O32>(a, w, lane, L, st, none, true);
 }
 
 __device__ __forceinline__ int entry_of(const BatchArgs& ba, int g)
@@ -887,21 +888,54 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_batch_kernel(BatchArgs b
     }
 }
 
-// Persistent LDS-DMA kernel: workgroup j of XCD x takes the items
-// slice[x] + j, slice[x] + j + P, ... (P workgroups per XCD; a static
-// schedule needs no atomics, so the next item is known in advance) and copies
-// the next item's first steps while it finishes the current one.
+// Persistent LDS-DMA kernel: the workgroups of XCD x take the items of
+// slice [slice[x], slice[x+1]) from the XCD's counter (zero before the
+// launch), one item ahead: a workgroup claims its next item when it starts
+// the current one and reads the claim after the current item's steps, when
+// every copy has landed, so the next item's first steps are still copied
+// before the current epilogue.  A workgroup that starts late, or a CU that
+// is busy with other work, then takes fewer items instead of holding up a
+// fixed share of them.
+template <int FMT>
+struct PersistNext {
+    const BatchArgs& ba;
+    int* s_claim;                  // LDS slot that broadcasts the claim
+    int claim;                     // thread 0: the counter value it claimed
+    int lo, hi, lane;
+    bool has;
+    int g, e;
+    WaveJobT<kWaves> w;
+    Stager<FMT> st;
+
+    __device__ __forceinline__ void operator()(const Bufs& L)
+    {
+        if (threadIdx.x == 0) *s_claim = lo + claim;
+        dma_barrier<0>();
+        g = __builtin_amdgcn_readfirstlane(*s_claim);
+        has = g < hi;
+        if (has) {
+            e = entry_of(ba, g);
+            w = wave_job<kWaves>(ba.e[e], g - ba.first[e]);
+            st.init(ba.e[e], w, lane);
+#pragma unroll
+            for (int s = 0; s < dma_depth(FMT); ++s) st.load(L.p[s], s);
+        }
+    }
+};
+
 template <int FMT, int O32>
 __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_persist_kernel(BatchArgs ba)
 {
     static_assert(is_dma(FMT), "persistent schedule of the LDS-DMA variants");
     const Bufs L = lds_buffers<FMT>();
+    __shared__ int s_claim;
     const int q = ba.xcd_map ? (int)(blockIdx.x & 7) : 0;
-    const int j = ba.xcd_map ? (int)(blockIdx.x >> 3) : (int)blockIdx.x;
-    const int P = ba.xcd_map ? (int)(gridDim.x >> 3) : (int)gridDim.x;
     const int lo = ba.xcd_map ? ba.slice[q] : ba.slice[0];
     const int hi = ba.xcd_map ? ba.slice[q + 1] : ba.slice[8];
-    int g = lo + j;
+    int* counter = ba.counters + q;
+    if (threadIdx.x == 0) s_claim = lo + atomicAdd(counter, 1);
+    __syncthreads();
+    int g = __builtin_amdgcn_readfirstlane(s_claim);
     if (g >= hi) return;
     const int lane = threadIdx.x & 63;
     int e = entry_of(ba, g);
@@ -910,22 +944,14 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_persist_kernel(BatchArgs
     st.init(ba.e[e], w, lane);
     bool issue = true;
     for (;;) {
-        const int gn = g + P;
-        const bool has_next = gn < hi;
-        int en = e;
-        WaveJobT<kWaves> wn = w;
-        Stager<FMT> nst = st;
-        if (has_next) {
-            en = entry_of(ba, gn);
-            wn = wave_job<kWaves>(ba.e[en], gn - ba.first[en]);
-            nst.init(ba.e[en], wn, lane);
-        }
-        dispatch_kind<FMT, O32>(ba.e[e], w, lane, L, st, has_next, nst, issue);
-        if (!has_next) break;
-        g = gn;
-        e = en;
-        w = wn;
-        st = nst;
+        PersistNext<FMT> next{ba, &s_claim, 0, lo, hi, lane, false, 0, 0, w, st};
+        if (threadIdx.x == 0) next.claim = atomicAdd(counter, 1);
+        dispatch_kind<FMT, O32>(ba.e[e], w, lane, L, st, next, issue);
+        if (!next.has) break;
+        g = next.g;
+        e = next.e;
+        w = next.w;
+        st = next.st;
         issue = false;
     }
 }
@@ -957,10 +983,13 @@ hipError_t launch_batch_variant(const BatchArgs& ba, int grid, hipStream_t s)
 
 // A single plan's chunk as a one-entry persistent launch (LDS-DMA variants).
 template <int FMT>
-hipError_t launch_persist_single(const LaunchArgs& a, int grid, hipStream_t s)
+hipError_t launch_persist_single(const LaunchArgs& a, int grid, int* counters, hipStream_t s)
 {
+    hipError_t e = launch_fill_zero(counters, 8 * sizeof(int), s);
+    if (e != hipSuccess) return e;
     BatchArgs ba;
     __builtin_memset(&ba, 0, sizeof ba);
+    ba.counters = counters;
     ba.n_entries = 1;
     ba.n_blocks = a.n_blocks;
     ba.xcd_map = a.xcd_map;
@@ -983,16 +1012,16 @@ int variant_of(int fmt, int n_inputs, int tile)
 
 }  // namespace
 
-hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, hipStream_t s)
+hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, int* counters, hipStream_t s)
 {
     switch (variant_of(fmt, a.n_inputs, tile)) {
     case V_CI8:      return launch_variant<V_CI8>(a, s);
     case V_CI4:      return launch_variant<V_CI4>(a, s);
-    case V_CI8_DMA4: return persist_grid ? launch_persist_single<V_CI8_DMA4>(a, persist_grid, s)
+    case V_CI8_DMA4: return persist_grid ? launch_persist_single<V_CI8_DMA4>(a, persist_grid, counters, s)
                                          : launch_variant<V_CI8_DMA4>(a, s);
-    case V_CI4_DMA4: return persist_grid ? launch_persist_single<V_CI4_DMA4>(a, persist_grid, s)
+    case V_CI4_DMA4: return persist_grid ? launch_persist_single<V_CI4_DMA4>(a, persist_grid, counters, s)
                                          : launch_variant<V_CI4_DMA4>(a, s);
-    default:         return persist_grid ? launch_persist_single<V_CI4_DMA8>(a, persist_grid, s)
+    default:         return persist_grid ? launch_persist_single<V_CI4_DMA8>(a, persist_grid, counters, s)
                                          : launch_variant<V_CI4_DMA8>(a, s);
     }
 }

@@ -159,7 +159,8 @@ constexpr int kWavesF32 = 4;
 // Kernel launchers (one per arithmetic path); return the launch error.
 // persist_grid > 0: LDS-DMA variants run as a persistent launch of that many
 // workgroups (a multiple of 8); 0: one workgroup per work item.
-hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, hipStream_t s);
+// counters: 8 device ints the persistent launch's work queue uses (zeroed here).
+hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, int* counters, hipStream_t s);
 hipError_t launch_i8_batch(const BatchArgs& ba, int fmt, int tile, int grid, hipStream_t s);
 hipError_t launch_i8w4(const BatchArgs& ba, int grid, hipStream_t s);
 hipError_t launch_f16(const LaunchArgs& a, int fmt, hipStream_t s);
