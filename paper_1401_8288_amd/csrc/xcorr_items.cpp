@@ -236,19 +236,19 @@ void plan_items8_paired(int W, std::vector<WorkItem>& items, int& ch_group)
 
 // Work items of a plan: items / ch_group for launches that write their
 // result (reset, dump), items_src / cg_src for launches that add to an
-// accumulator.  4-bit int8 plans pair the diagonal items of two channels in
-// the first table only: pairing made adding launches 6 % slower at the LWA
+// accumulator.  int8 plans pair the diagonal items of two channels in the
+// first table only: pairing made adding launches 6 % slower at the LWA
 // size (their epilogue reads the accumulator, and the 10-block waves of the
-// shared items make it longer).  8-bit plans keep one channel per item in
-// both, because the paired list made the 2048-input 8-bit window 6 % slower
-// (twice the channels in flight per XCD for samples twice as wide).
-void plan_items(int path, int tile, int fmt, int W, std::vector<WorkItem>& items, int& ch_group,
+// shared items make it longer).  (With a static schedule the paired list
+// also made the 2048-input 8-bit window 6 % slower, from L2 misses; with
+// the per-XCD queue it makes it 1 % faster.)
+void plan_items(int path, int tile, int /*fmt*/, int W, std::vector<WorkItem>& items, int& ch_group,
                 std::vector<WorkItem>& items_src, int& cg_src)
 {
     const bool i8 = path == XCORR_PATH_I8_MFMA && tile != kTileW4;
     if (i8) plan_items8(W, items_src, cg_src);
     else plan_items4(W, items_src, cg_src);
-    if (i8 && fmt == XCORR_CI4 && W > 1) {
+    if (i8 && W > 1) {
         plan_items8_paired(W, items, ch_group);
     } else {
         items = items_src;

@@ -391,7 +391,7 @@ def test_many_inputs_one_channel(fmt):
 @pytest.mark.parametrize("shape", [(128, 1, 200), (192, 3, 129), (320, 5, 64), (256, 2, 300), (448, 7, 70),
                                    (100, 3, 90)], ids=lambda s: "x".join(map(str, s)))
 def test_4bit_items_pair_diagonals_of_two_channels(tile, shape):
-    # 4-bit plans put the diagonal tiles of two channels into one work item;
+    # int8 plans put the diagonal tiles of two channels into one work item;
     # odd channel counts leave the second channel of the last group empty,
     # odd row-block counts end with a single-block diagonal item
     n_in, n_ch, n_t = shape
