@@ -387,30 +387,30 @@ def test_many_inputs_one_channel(fmt):
     np.testing.assert_array_equal(got32.astype(np.int64), ref)
 
 
-@pytest.mark.parametrize("tile", [0, 1, 3])
+@pytest.mark.parametrize("fmt,tile", [("ci4", 0), ("ci4", 1), ("ci4", 3), ("ci8", 0), ("ci8", 3)])
 @pytest.mark.parametrize("shape", [(128, 1, 200), (192, 3, 129), (320, 5, 64), (256, 2, 300), (448, 7, 70),
                                    (100, 3, 90)], ids=lambda s: "x".join(map(str, s)))
-def test_4bit_items_pair_diagonals_of_two_channels(tile, shape):
+def test_int8_items_pair_diagonals_of_two_channels(fmt, tile, shape):
     # int8 plans put the diagonal tiles of two channels into one work item;
     # odd channel counts leave the second channel of the last group empty,
     # odd row-block counts end with a single-block diagonal item
     n_in, n_ch, n_t = shape
     if tile == 1 and n_in % 16:
         pytest.skip("the LDS-DMA tiles need n_inputs % 16 == 0")
-    say("paired diagonal items", shape, "tile", tile)
-    x = synth.random_input(n_ch, n_t, n_in, "ci4", seed=n_in + n_ch, device=DEV)
-    ref = oracle.correlate(x.cpu().numpy(), "ci4")
-    p = xc().Plan(n_in, n_ch, "ci4", "i8", tile=tile)
+    say("paired diagonal items", fmt, shape, "tile", tile)
+    x = synth.random_input(n_ch, n_t, n_in, fmt, seed=n_in + n_ch, device=DEV)
+    ref = oracle.correlate(x.cpu().numpy(), fmt)
+    p = xc().Plan(n_in, n_ch, fmt, "i8", tile=tile)
     assert p.query().channels_per_group == 2
     p.close()
-    got, _ = run(x, "ci4", "i8", tile=tile)
+    got, _ = run(x, fmt, "i8", tile=tile)
     np.testing.assert_array_equal(got, ref)
-    got32, _ = run(x, "ci4", "i8", tile=tile, flags=xc().FLAG_OUT_I32)
+    got32, _ = run(x, fmt, "i8", tile=tile, flags=xc().FLAG_OUT_I32)
     np.testing.assert_array_equal(got32.astype(np.int64), ref)
     # launches that add to the accumulator take the single-channel items,
     # launches that write their result the paired ones: mix both in a window
     k = n_t // 3
-    p = xc().Plan(n_in, n_ch, "ci4", "i8", tile=tile)
+    p = xc().Plan(n_in, n_ch, fmt, "i8", tile=tile)
     p.accumulate(x[:, :k].contiguous())
     p.accumulate(x[:, k:2 * k].contiguous())
     out, info = p.accumulate_dump(x[:, 2 * k:].contiguous())
