@@ -256,10 +256,10 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
 }
 
 // work[m][a][cp] -> out[c][m][a] (c = cp - (chan_begin - base)), bytes.  A
-// workgroup moves a 128-input x 128-channel tile of one spectrum: dword
+// workgroup moves a 128-input x 128-channel tile of one spectrum: 16-byte
 // loads along channels, 4 x 4 byte transposes in registers, an LDS tile of
 // [input / 4][channel] dwords, and 16-byte stores along inputs, eight lanes
-// to a 128-byte output row.
+// to a 128-byte row on both sides.
 __global__ void __launch_bounds__(kThreads) fstage_transpose_kernel(FstageArgs a)
 {
     __shared__ uint32_t T[32][128 + 4];
@@ -276,28 +276,33 @@ __global__ void __launch_bounds__(kThreads) fstage_transpose_kernel(FstageArgs a
     const uint8_t* w = (const uint8_t*)a.work;
 
     {
-        const int c4 = t & 31, aq = t >> 5;      // channels cp0 + 4 c4 .. + 3, inputs a0 + 16 aq ..
-        const int cp = cp0 + 4 * c4;
+        // 16-byte loads: lane (c16, aq) reads channels cp0 + 16 c16 .. + 15
+        // of inputs a0 + 4 aq .. + 3; eight lanes cover a 128-byte row
+        const int c16 = t & 7, aq = t >> 3;
+        const int cp = cp0 + 16 * c16;
+        uint4 r[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            uint32_t r[4];
+        for (int k = 0; k < 4; ++k) {
+            const int ar = a0 + 4 * aq + k;
+            r[k] = (ar < a.n_inputs && cp < a.cp)
+                       ? *(const uint4*)(w + ((int64_t)m * a.n_inputs + ar) * a.cp + cp) : make_uint4(0, 0, 0, 0);
+        }
+        const uint32_t* rr[4] = {&r[0].x, &r[1].x, &r[2].x, &r[3].x};
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int ar = a0 + 16 * aq + 4 * i + k;
-                r[k] = (ar < a.n_inputs && cp < a.cp)
-                           ? *(const uint32_t*)(w + ((int64_t)m * a.n_inputs + ar) * a.cp + cp) : 0u;
-            }
-            // 4 x 4 byte transpose: column cc = (r0[cc], r1[cc], r2[cc], r3[cc])
-            const uint32_t t0 = __builtin_amdgcn_perm(r[1], r[0], 0x05010400u);
-            const uint32_t t1 = __builtin_amdgcn_perm(r[1], r[0], 0x07030602u);
-            const uint32_t t2 = __builtin_amdgcn_perm(r[3], r[2], 0x05010400u);
-            const uint32_t t3 = __builtin_amdgcn_perm(r[3], r[2], 0x07030602u);
+        for (int j = 0; j < 4; ++j) {
+            // 4 x 4 byte transpose of channels 4 j .. + 3: column cc holds
+            // the four inputs of channel 4 j + cc
+            const uint32_t r0 = rr[0][j], r1 = rr[1][j], r2 = rr[2][j], r3 = rr[3][j];
+            const uint32_t t0 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);
+            const uint32_t t1 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);
+            const uint32_t t2 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+            const uint32_t t3 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
             uint4 col;
             col.x = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
             col.y = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
             col.z = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
             col.w = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
-            *(uint4*)&T[4 * aq + i][4 * c4] = col;
+            *(uint4*)&T[aq][16 * c16 + 4 * j] = col;
         }
     }
     __syncthreads();
