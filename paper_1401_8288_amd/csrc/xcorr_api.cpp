@@ -378,7 +378,8 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
 
     e = hipMalloc(&p->acc, p->out_bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, p->n_items_stored * sizeof(WorkItem));
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_counters, 8 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_counters, kCounterInts * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(p->d_counters, 0, kCounterInts * sizeof(int));
     if (e != hipSuccess) {
         release(p->acc);
         release(p->d_items);

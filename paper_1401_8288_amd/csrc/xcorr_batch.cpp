@@ -19,7 +19,7 @@ struct xcorr_batch_s {
     int format = 0;
     bool dma_ok = false;            // every plan allows the LDS-DMA tiles
     int n_cu = 256;
-    int* d_counters = nullptr;      // 8 per-XCD work counters
+    int* d_counters = nullptr;      // kCounterInts work-queue counters
     xcorr_batch_config cfg{};
 };
 
@@ -124,8 +124,7 @@ xcorr_status launch_entries_same_width(xcorr_batch_t b, const std::vector<Entry>
         ba.n_blocks = total;
         ba.counters = b->d_counters;
         make_slices(part, ba.first, total, cfg.balance, ba.slice);
-        hipError_t err = launch_fill_zero(b->d_counters, 8 * sizeof(int), b->stream);
-        if (err == hipSuccess) err = launch_i8_batch(ba, b->format, cfg.tile, cfg.grid, b->stream);
+        hipError_t err = launch_i8_batch(ba, b->format, cfg.tile, cfg.grid, b->stream);
         if (err != hipSuccess) return hip_fail(err, "batch launch");
     }
     return XCORR_OK;
@@ -281,8 +280,10 @@ xcorr_status xcorr_batch_create(xcorr_batch_t* out, const xcorr_plan_t* plans, i
     b->cfg.tile = dma_ok ? kTileDma4 : kTileRegs;
     b->cfg.grid = ((b->n_cu + 7) / 8) * 8;
     b->cfg.balance = 1;
-    e = hipMalloc((void**)&b->d_counters, 8 * sizeof(int));
+    e = hipMalloc((void**)&b->d_counters, kCounterInts * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(b->d_counters, 0, kCounterInts * sizeof(int));
     if (e != hipSuccess) {
+        if (b->d_counters) (void)hipFree(b->d_counters);
         delete b;
         (void)hipGetLastError();
         return fail(XCORR_ERR_NOMEM, "batch counters: %s", hipGetErrorString(e));

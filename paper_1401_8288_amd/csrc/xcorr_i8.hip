@@ -863,11 +863,23 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_kernel(LaunchArgs a)
     process_item<FMT, O32>(a, b, L);
 }
 
+// The last workgroup to leave a launch that takes items from the per-XCD
+// counters zeroes them for the next launch on the stream: every workgroup has taken its last claim before
+// it counts itself out (counters[8]), so no claim follows the reset.
+__device__ __forceinline__ void finish_queue(int* counters)
+{
+    if (threadIdx.x == 0 && atomicAdd(counters + 8, 1) == (int)gridDim.x - 1) {
+#pragma unroll
+        for (int q = 0; q <= 8; ++q) counters[q] = 0;
+    }
+}
+
 // Persistent launch over the work items of several plans (subarrays of uneven
 // size and window length).  The items of all entries form one list; XCD x
 // owns the slice [slice[x], slice[x+1]) (contiguous, so a channel's workgroups
 // share that XCD's L2) and its workgroups take items from it in order through
-// the XCD's counter.  Every workgroup leaves once its slice is exhausted.
+// the XCD's counter.  Every workgroup leaves once its slice is exhausted;
+// the last one zeroes the counters.
 template <int FMT, int O32>
 __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_batch_kernel(BatchArgs ba)
 {
@@ -886,11 +898,12 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_batch_kernel(BatchArgs b
         const int e = entry_of(ba, g);
         process_item<FMT, O32>(ba.e[e], g - ba.first[e], L);
     }
+    finish_queue(ba.counters);
 }
 
 // Persistent LDS-DMA kernel: the workgroups of XCD x take the items of
-// slice [slice[x], slice[x+1]) from the XCD's counter (zero before the
-// launch), one item ahead: a workgroup claims its next item when it starts
+// slice [slice[x], slice[x+1]) from the XCD's counter (zero when the launch
+// starts; the launch leaves it zero), one item ahead: a workgroup claims its next item when it starts
 // the current one and reads the claim after the current item's steps, when
 // every copy has landed, so the next item's first steps are still copied
 // before the current epilogue.  A workgroup that starts late, or a CU that
@@ -936,7 +949,10 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_persist_kernel(BatchArgs
     if (threadIdx.x == 0) s_claim = lo + atomicAdd(counter, 1);
     __syncthreads();
     int g = __builtin_amdgcn_readfirstlane(s_claim);
-    if (g >= hi) return;
+    if (g >= hi) {
+        finish_queue(ba.counters);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     int e = entry_of(ba, g);
     WaveJobT<kWaves> w = wave_job<kWaves>(ba.e[e], g - ba.first[e]);
@@ -954,6 +970,7 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_persist_kernel(BatchArgs
         st = next.st;
         issue = false;
     }
+    finish_queue(ba.counters);
 }
 
 template <int FMT>
@@ -985,8 +1002,6 @@ hipError_t launch_batch_variant(const BatchArgs& ba, int grid, hipStream_t s)
 template <int FMT>
 hipError_t launch_persist_single(const LaunchArgs& a, int grid, int* counters, hipStream_t s)
 {
-    hipError_t e = launch_fill_zero(counters, 8 * sizeof(int), s);
-    if (e != hipSuccess) return e;
     BatchArgs ba;
     __builtin_memset(&ba, 0, sizeof ba);
     ba.counters = counters;
@@ -1034,8 +1049,8 @@ hipError_t launch_i8_batch(const BatchArgs& ba, int fmt, int tile, int grid, hip
     for (int e = 0; e < ba.n_entries; ++e) n16 &= ba.e[e].n_inputs % 16 == 0;
     // 8-bit batches stay on the register-staged kernel: the two-plane
     // layout of V_CI8_DMA4 is made by the single-plan launch path only
-    if (fmt == 1) return launch_batch_variant<V_CI8>(ba, grid, s);
-    switch (variant_of(fmt, n16 ? 16 : 4, tile)) {
+    const int v = fmt == 1 ? V_CI8 : variant_of(fmt, n16 ? 16 : 4, tile);
+    switch (v) {
     case V_CI8:      return launch_batch_variant<V_CI8>(ba, grid, s);
     case V_CI4:      return launch_batch_variant<V_CI4>(ba, grid, s);
     case V_CI4_DMA4: return launch_batch_variant<V_CI4_DMA4>(ba, grid, s);

@@ -133,6 +133,9 @@ inline int launch_blocks(int n_blocks, int xcd_map)
 // Arguments of one persistent batch launch: the launch arguments of up to
 // kMaxBatchEntries (plan, time chunk) entries, passed by value.
 constexpr int kMaxBatchEntries = 24;
+// Work-queue counters of a launch: one per XCD and one count of finished
+// workgroups (allocated zero; a persistent launch leaves them zero).
+constexpr int kCounterInts = 16;
 struct BatchArgs {
     int32_t n_entries;
     int32_t n_blocks;              // total work items over all entries
@@ -140,7 +143,7 @@ struct BatchArgs {
     int32_t pad;
     int32_t first[kMaxBatchEntries + 1];   // first global item of each entry
     int32_t slice[9];              // XCD x takes items [slice[x], slice[x+1])
-    int* counters;                 // 8 device counters, zero before the launch
+    int* counters;                 // kCounterInts device ints, zero when the launch starts
     LaunchArgs e[kMaxBatchEntries];
 };
 
@@ -159,7 +162,8 @@ constexpr int kWavesF32 = 4;
 // Kernel launchers (one per arithmetic path); return the launch error.
 // persist_grid > 0: LDS-DMA variants run as a persistent launch of that many
 // workgroups (a multiple of 8); 0: one workgroup per work item.
-// counters: 8 device ints the persistent launch's work queue uses (zeroed here).
+// counters: kCounterInts device ints, zero, that the persistent launch's work
+// queue uses and leaves zero.
 hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, int* counters, hipStream_t s);
 hipError_t launch_i8_batch(const BatchArgs& ba, int fmt, int tile, int grid, hipStream_t s);
 hipError_t launch_i8w4(const BatchArgs& ba, int grid, hipStream_t s);

@@ -293,8 +293,10 @@ xcorr_status xcorr_server_create(xcorr_server_t* out, const xcorr_server_desc* d
     s->device = dev;
     s->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     s->stream = (hipStream_t)d->stream;
-    e = hipMalloc((void**)&s->d_counters, 8 * sizeof(int));
+    e = hipMalloc((void**)&s->d_counters, kCounterInts * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(s->d_counters, 0, kCounterInts * sizeof(int));
     if (e != hipSuccess) {
+        if (s->d_counters) (void)hipFree(s->d_counters);
         delete s;
         (void)hipGetLastError();
         return fail(XCORR_ERR_NOMEM, "server counters: %s", hipGetErrorString(e));
