@@ -154,6 +154,33 @@ def pmc_summary(directory):
         print("%-70s %-30s dispatches=%d avg=%.6g" % (k[:70], c, len(v), sum(v) / len(v)))
 
 
+def trace_summary(directory, skip, take, match):
+    """Per-kernel durations of rocprofv3 kernel-trace CSVs under a directory:
+    for every kernel whose name contains `match`, its dispatches in start
+    order, the first `skip` left out (warm-up windows) and the next `take`
+    averaged (the timed windows; all the rest if take is 0).  Prints a
+    markdown table."""
+    import collections
+    import csv
+    import glob
+    runs = collections.OrderedDict()
+    for f in sorted(glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)):
+        for r in csv.DictReader(open(f)):
+            if match and match not in r["Kernel_Name"]:
+                continue
+            runs.setdefault(r["Kernel_Name"], []).append(
+                (int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    print("| Kernel | Dispatches | Used | Average ns | Min ns | Max ns |")
+    print("|---|---|---|---|---|---|")
+    for k, v in runs.items():
+        d = [dt for _, dt in sorted(v)]
+        sel = d[skip:skip + take] if take else d[skip:]
+        if not sel:
+            continue
+        print("| `%s` | %d | %d..%d | %d | %d | %d |" % (k[:90], len(d), skip, skip + len(sel) - 1,
+                                                      sum(sel) // len(sel), min(sel), max(sel)))
+
+
 def copy_calibration(torch, xcorr, x, w):
     """One non-fused window, then a dump without reset: the library's copy
     kernel moves exactly output_bytes (read and written)."""
@@ -295,7 +322,11 @@ def fstage_leg(torch, xcorr, w, reps=3, n_taps=2):
     samples = w.n_inputs * w.n_time * N
     flops = samples * (2 * n_taps + 2.5 * 13)
     codes = w.n_inputs * w.n_time * w.n_channels
-    nbytes = w.n_inputs * n_samples + 3 * codes
+    # algorithmic HBM bytes: the ADC samples read once and the codes written
+    # once; the transpose pass's write and read-back of the input-major codes
+    # is reported beside it, not counted as useful traffic
+    nbytes = w.n_inputs * n_samples + codes
+    extra = 2 * codes
     del adc, out, work
     torch.cuda.empty_cache()
     return {"config": "%d inputs, %d-tap %d-point PFB, %d channels, %d spectra, CI4 out in X-stage order"
@@ -304,7 +335,8 @@ def fstage_leg(torch, xcorr, w, reps=3, n_taps=2):
             "bound": "alu", "achieved": round(flops / ms / 1e9, 2), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(flops / ms / 1e9 / PEAK_FP32_TFLOPS, 4),
             "algorithmic_flops_per_sample": 2 * n_taps + 2.5 * 13,
-            "hbm_bytes": nbytes, "hbm_gbs": round(nbytes / ms / 1e6, 1)}
+            "hbm_bytes": nbytes, "hbm_gbs": round(nbytes / ms / 1e6, 1),
+            "transpose_extra_bytes": extra}
 
 
 def variants_leg(torch, xcorr, x, w, reps=3, period=700, on=0.09):
@@ -349,6 +381,16 @@ def variants_leg(torch, xcorr, x, w, reps=3, period=700, on=0.09):
                           "gbs": round(3 * frac * w.output_bytes / ms_tiles / 1e6, 1)}}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The oracle on a bounded sample of the same workload (host cores)."""
     import oracle
@@ -366,7 +408,7 @@ def cpu_baseline(w, budget_s=12.0):
     dt = time.perf_counter() - t0
     cmac = sample.cmac * reps
     return {"value": round(cmac / dt / 1e12, 6), "unit": "TCMAC/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "compiler": oracle.compiler(),
             "sample": "%d passes over %d channels x %d inputs x %d samples (%.3g CMAC, %.1f s)"
                       % (reps, sample.n_channels, w.n_inputs, w.n_time, cmac, dt)}
 
@@ -391,9 +433,18 @@ def main():
                     help="also run the library copy kernel once (for counter calibration)")
     ap.add_argument("--pmc-summary", metavar="DIR",
                     help="print per-kernel averages of rocprofv3 counter CSVs and exit")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="print per-kernel durations of rocprofv3 kernel-trace CSVs and exit "
+                         "(with --trace-skip / --trace-take / --trace-match)")
+    ap.add_argument("--trace-skip", type=int, default=0, help="dispatches of each kernel left out first")
+    ap.add_argument("--trace-take", type=int, default=0, help="dispatches averaged after those (0: all)")
+    ap.add_argument("--trace-match", default="", help="only kernels whose name contains this")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.trace_skip, args.trace_take, args.trace_match)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the X-stage shards by channel with no exchange, "

@@ -434,6 +434,10 @@ xcorr_status xcorr_graph_launch(xcorr_graph_t g)
     if (!graph_live(g)) return fail(XCORR_ERR_STATE, "invalid graph handle");
     xcorr_batch_t b = g->batch;
     if (!batch_live(b)) return fail(XCORR_ERR_STATE, "the graph's batch was destroyed");
+    // the replay writes every plan's bookkeeping (and, past the fold bound,
+    // its accumulator): refuse it once any of them was destroyed
+    for (size_t k = 0; k < b->plans.size(); ++k)
+        if (!plan_live(b->plans[k])) return fail(XCORR_ERR_STATE, "plan %zu of the graph's batch was destroyed", k);
     hipError_t e = hipGraphLaunch(g->exec, b->stream);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
     for (size_t k = 0; k < b->plans.size(); ++k) {

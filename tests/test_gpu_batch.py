@@ -235,3 +235,70 @@ def test_batch_errors():
     b.close()
     for p in (p1, p2, p3):
         p.close()
+
+
+def test_graph_launch_after_a_plan_was_destroyed_is_refused():
+    # a replay writes every plan's bookkeeping; once a plan is gone the
+    # launch must fail before anything is enqueued
+    say("batch: graph launch after destroying one of its plans")
+    X = xc()
+    subs = [(32, 2, 128), (64, 1, 200)]
+    xs = inputs(subs, seed=81)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plans = [X.Plan(n, c, "ci4", "i8", stream=s) for (n, c, _) in subs]
+        b = X.Batch(plans, stream=s)
+        outs = [p.new_output() for p in plans]
+    torch.cuda.synchronize()
+    g = b.capture(xs, outs)
+    g.launch()
+    s.synchronize()
+    plans[1].close()
+    with pytest.raises(X.XcorrError) as ei:
+        g.launch()
+    assert ei.value.status == -4
+    g.close()
+    b.close()
+    plans[0].close()
+
+
+def test_work_queue_counters_survive_changes_of_launch_configuration():
+    # every persistent launch takes items from the same per-XCD counters and
+    # the last workgroup of each launch zeroes them: launches of different
+    # grids, slice balances and XCD maps on one counter set, back to back,
+    # must each cover all of their items
+    say("batch: alternating persistent launch configurations on one counter set")
+    X = xc()
+    xs = inputs(SUBS[:3], seed=91)
+    refs = oracle_of(xs)
+    plans, b = make(SUBS[:3])
+    outs = [p.new_output() for p in plans]
+    configs = [(0, 512, 1), (2, 256, 0), (1, 256, 1), (0, 1024, 0), (3, 512, 1), (0, 256, 1)]
+    for cfg in configs:
+        b.set_config(*cfg)
+        for o in outs:
+            o.fill_(-1)
+        b.run(xs, outs)
+        for (n, c, t), x, r in zip(SUBS[:3], xs, refs):
+            # a single plan on the same stream between the batch steps
+            p = X.Plan(n, c, "ci4", "i8")
+            got, _ = p.accumulate_dump(x)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(got.cpu().numpy(), r, err_msg="single plan after config %s" % (cfg,))
+            p.close()
+        torch.cuda.synchronize()
+        for k, (o, r) in enumerate(zip(outs, refs)):
+            np.testing.assert_array_equal(o.cpu().numpy(), r, err_msg="config %s sub %d" % (cfg, k))
+    close(plans, b)
+    # the same counters of one plan: persistent launches with and without the
+    # XCD map, one workgroup per item, then persistent again
+    x = xs[2]
+    n, c, t = SUBS[2]
+    for flags in (0, X.FLAG_NO_XCD_MAP, X.FLAG_NO_PERSIST, X.FLAG_NO_XCD_MAP | X.FLAG_OUT_I32, 0):
+        p = X.Plan(n, c, "ci4", "i8", flags=flags)
+        for rep in range(2):
+            got, _ = p.accumulate_dump(x)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(got.cpu().numpy().astype(np.int64), refs[2],
+                                          err_msg="flags %#x rep %d" % (flags, rep))
+        p.close()

@@ -325,6 +325,16 @@ def test_lwa_workload_full_size_int8(lwa):
         np.testing.assert_array_equal(got[c], oracle.correlate(x_np, w.fmt, (int(c), 1))[0])
     say("lwa beam-power identity on all channels")
     _beam_check(x_np, w.fmt, got, seeds=(201, 202))
+    del got
+    # the configuration the benchmark times: int32 (re, im) output, the
+    # persistent LDS-DMA kernel writing the dump directly
+    say("lwa int8 accumulate_dump, int32 output")
+    got32, info = run(x, w.fmt, "i8", flags=xc().FLAG_OUT_I32)
+    assert info.samples_accumulated == w.n_time and got32.dtype == np.int32
+    for c in list(ch) + [0, 1, w.n_channels - 1]:
+        np.testing.assert_array_equal(got32[c].astype(np.int64), oracle.correlate(x_np, w.fmt, (int(c), 1))[0])
+    say("lwa int32 output: beam-power identity on all channels")
+    _beam_check(x_np, w.fmt, got32, seeds=(203, 204))
 
 
 def test_lwa_workload_fp16_exact_on_sampled_channels(lwa):
