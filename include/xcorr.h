@@ -180,6 +180,33 @@ xcorr_status xcorr_plan_bytes(const xcorr_plan_desc* desc, size_t* bytes);
 /* Release the plan (waits for its stream).  Destroying NULL is XCORR_ERR_STATE. */
 xcorr_status xcorr_destroy(xcorr_plan_t plan);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * integration window, the same result as xcorr_plan + xcorr_accumulate_dump
+ * (reset) + xcorr_destroy with this descriptor, and the same kernels, but
+ * no plan and no allocation.  The state those kernels need besides the
+ * input and output -- the work-queue counters of the persistent launch and
+ * the work-item table -- lives in a 4 MiB array inside the library, one per
+ * GPU, kept until the process ends (its address is looked up once per
+ * device, on the first call with that device current).
+ *   desc   path XCORR_PATH_I8_MFMA, tile XCORR_TILE_DEFAULT; flags
+ *          XCORR_FLAG_OUT_I32 / NO_XCD_MAP / NO_PERSIST as for a plan; work
+ *          is enqueued on desc->stream.  n_inputs a multiple of 4 (CI4) or
+ *          2 (CI8), up to the input count whose work-item table fits the
+ *          array (87,376 items; every count up to 32768 fits).
+ *   d_in   device, [n_channels][n_time][n_inputs] as for xcorr_accumulate
+ *   d_out  device, [n_channels][n_inputs(n_inputs+1)/2][2], int64 (int32
+ *          with XCORR_FLAG_OUT_I32), written completely
+ * n_time must lie in [1, fold_bound] (one launch): longer windows need the
+ * plan's accumulator, and are refused with XCORR_ERR_ARG.  8-bit samples
+ * use the register-staged tile (the LDS-DMA tile reads a staged copy).
+ * Each call clears the counters (a fill kernel) and copies the table (a
+ * host-to-device copy of a table the library keeps for the process) before
+ * its kernel, all on desc->stream; no hipMalloc, hipFree or other
+ * allocating call is made.  Calls that overlap on one GPU share the array
+ * and race: order them on one stream or synchronise between them. */
+xcorr_status xcorr_correlate_noalloc(const xcorr_plan_desc* desc, const void* d_in, int64_t n_time, void* d_out);
+
 /* ------------------------------------------------------------------------
  * Corner turn (Sec. 2.4): the X-stage input of a GPU assembled from captured
  * F-engine packets.  Capture places each packet by its sequence number

@@ -36,7 +36,7 @@ EXPORTS = ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dum
            "xcorr_server_create", "xcorr_server_open", "xcorr_server_submit", "xcorr_server_poll",
            "xcorr_server_wait", "xcorr_server_close", "xcorr_server_query", "xcorr_server_destroy",
            "xcorr_corner_turn", "xcorr_dump_tiles", "xcorr_accumulate_gated", "xcorr_fstage",
-           "xcorr_fstage_work_bytes", "xcorr_clock_probe")
+           "xcorr_fstage_work_bytes", "xcorr_clock_probe", "xcorr_correlate_noalloc")
 
 
 class PlanDesc(ctypes.Structure):
@@ -143,6 +143,7 @@ def _load():
     L.xcorr_fstage.argtypes = [P(FstageDesc), vp, i64, i64, vp, vp, vp, vp, P(i64), vp]
     L.xcorr_fstage_work_bytes.argtypes = [P(FstageDesc), i64, P(ctypes.c_size_t)]
     L.xcorr_clock_probe.argtypes = [vp, i64, P(ctypes.c_int32), vp]
+    L.xcorr_correlate_noalloc.argtypes = [P(PlanDesc), vp, i64, vp]
     for name in EXPORTS:
         if name not in ("xcorr_strerror", "xcorr_last_error", "xcorr_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -310,6 +311,33 @@ def correlate(x: torch.Tensor, fmt: str = "ci4", path: str = "i8") -> torch.Tens
     n_ch, n_in = x.shape[0], x.shape[2]
     with Plan(n_in, n_ch, fmt, path) as p:
         out, _ = p.accumulate_dump(x)
+    return out
+
+
+def correlate_noalloc(x: torch.Tensor, fmt: str = "ci4", out: torch.Tensor | None = None, flags: int = 0,
+                      stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """One window through xcorr_correlate_noalloc (int8 path): the library
+    allocates no device memory; `out` (int64, or int32 with FLAG_OUT_I32) is
+    allocated here when not given."""
+    if fmt == "ci4":
+        if x.dtype != torch.uint8 or x.dim() != 3:
+            raise ValueError("ci4 input must be uint8 [channel][time][input]")
+    elif x.dtype != torch.int8 or x.dim() != 4 or x.shape[3] != 2:
+        raise ValueError("ci8 input must be int8 [channel][time][input][2]")
+    if not x.is_contiguous():
+        raise ValueError("input must be contiguous")
+    n_ch, n_t, n_in = x.shape[0], x.shape[1], x.shape[2]
+    dtype = torch.int32 if flags & FLAG_OUT_I32 else torch.int64
+    shape = (n_ch, n_in * (n_in + 1) // 2, 2)
+    if out is None:
+        out = torch.empty(shape, dtype=dtype, device=x.device)
+    elif out.dtype != dtype or tuple(out.shape) != shape or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("output must be a contiguous %s tensor %s on %s" % (dtype, shape, x.device))
+    stream = stream if stream is not None else torch.cuda.current_stream(x.device)
+    desc = make_desc(n_in, n_ch, fmt, "i8", stream, flags)
+    with torch.cuda.device(x.device):
+        _check(lib.xcorr_correlate_noalloc(ctypes.byref(desc), ctypes.c_void_p(int(x.data_ptr())), int(n_t),
+                                           ctypes.c_void_p(int(out.data_ptr()))))
     return out
 
 

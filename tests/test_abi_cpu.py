@@ -229,3 +229,18 @@ def test_clock_probe_argument_checks():
     assert L.xcorr_clock_probe(ctypes.c_void_p(0x1004), 100, None, None) == -1     # misaligned
     assert L.xcorr_clock_probe(ctypes.c_void_p(0x1000), 0, None, None) == -1
     assert L.xcorr_clock_probe(ctypes.c_void_p(0x1000), 1 << 32, None, None) == -1
+
+
+def test_noalloc_argument_checks_before_any_device_call():
+    from paper_1401_8288_amd import xcorr
+    L = xcorr.lib
+    p = ctypes.c_void_p(0x1000)
+    assert L.xcorr_correlate_noalloc(None, p, 64, p) == -1
+    assert L.xcorr_correlate_noalloc(ctypes.byref(_desc(path="f32")), p, 64, p) == -6
+    assert L.xcorr_correlate_noalloc(ctypes.byref(_desc(n_inputs=6)), p, 64, p) == -6
+    assert L.xcorr_correlate_noalloc(ctypes.byref(_desc(tile=1)), p, 64, p) == -6
+    assert L.xcorr_correlate_noalloc(ctypes.byref(_desc(flags=0x100)), p, 64, p) == -1
+    assert L.xcorr_correlate_noalloc(ctypes.byref(_desc()), p, 0, p) == -1           # empty window
+    assert L.xcorr_correlate_noalloc(ctypes.byref(_desc()), p, 65536, p) == -1       # past the fold bound
+    assert L.xcorr_correlate_noalloc(ctypes.byref(_desc()), None, 64, p) == -1
+    assert L.xcorr_correlate_noalloc(ctypes.byref(_desc()), ctypes.c_void_p(0x1008), 64, p) == -1
