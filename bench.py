@@ -46,7 +46,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_path(torch, xcorr, x, w, path, steps, warmup, flags=0, per_step=None, clock=None):
+def time_path(torch, xcorr, x, w, path, steps, warmup, flags=0, per_step=None, clock=None, tile=0):
     """Average ms of one accumulate_dump window on the plan's stream (HIP
     events around all steps).  If per_step is a list, the ms of each step
     (events between steps) are appended to it.  If clock is a dict, after
@@ -54,7 +54,7 @@ def time_path(torch, xcorr, x, w, path, steps, warmup, flags=0, per_step=None, c
     side stream beside them, and clock["mhz"] receives the shader clock it
     saw (the probe is kept out of the timed steps: its wave shares a CU with
     one workgroup of the persistent launch)."""
-    p = xcorr.Plan(w.n_inputs, w.n_channels, w.fmt, path, flags=flags)
+    p = xcorr.Plan(w.n_inputs, w.n_channels, w.fmt, path, flags=flags, tile=tile)
     out = p.new_output()
     for _ in range(warmup):
         p.accumulate_dump(x, out)
@@ -425,6 +425,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the gating / tile-dump leg")
     ap.add_argument("--workload", default="lwa",
                     help="synthetic workload of the timed window (default lwa, the headline; others for profiling)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="int8 tile variant of the timed plans (XCORR_TILE_*; 0 = the library's default)")
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="length of the batched-streaming leg (0 skips it)")
     ap.add_argument("--serving-speedup", type=float, default=40.0,
@@ -468,7 +470,7 @@ def main():
     steps_ms = []
     clock = {}
     ms, out, info = time_path(torch, xcorr, x, w, "i8", args.steps, args.warmup, flags=xcorr.FLAG_OUT_I32,
-                              per_step=steps_ms, clock=clock)
+                              per_step=steps_ms, clock=clock, tile=args.tile)
     cmac = w.cmac
     tcmac = cmac / (ms * 1e-3) / 1e12
     tops = 8 * cmac / (ms * 1e-3) / 1e12
@@ -481,7 +483,7 @@ def main():
     del out
     torch.cuda.empty_cache()
     log("int8 MFMA path, int64 output: %d warmup + %d timed windows" % (args.warmup, args.steps))
-    ms64, out64, _ = time_path(torch, xcorr, x, w, "i8", args.steps, args.warmup)
+    ms64, out64, _ = time_path(torch, xcorr, x, w, "i8", args.steps, args.warmup, tile=args.tile)
     del out64
     tops64 = 8 * cmac / (ms64 * 1e-3) / 1e12
     log("int8, int64 out: %.3f ms/window, %.1f%% of int8 peak" % (ms64, 100 * tops64 / PEAK_INT8_TOPS))

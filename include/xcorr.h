@@ -74,7 +74,7 @@ typedef enum {
  * would take).  Exact for any window of at most fold_bound samples between
  * resets, for both formats (the largest CI8 sums stay below 2^31); a call
  * that would take a window past fold_bound fails with XCORR_ERR_ARG and
- * changes nothing.  Not with the fp paths or XCORR_TILE_W4. */
+ * changes nothing.  Not with the fp paths. */
 
 /* Tile variants of the int8 path (xcorr_plan_desc.tile).  All give identical
  * (exact) results; they differ in how samples reach LDS. */
@@ -89,13 +89,12 @@ typedef enum {
  * ordered after the work already on the plan's stream, and the kernel of
  * each group waits on the plan's stream for that group's split; the
  * calls return with all their work ordered on the plan's stream, as usual.
- * Batches of 8-bit plans use the register tile.  DMA8 and W4 take 4-bit
- * samples only. */
+ * Batches of 8-bit plans use the register tile.  DMA8 takes 4-bit samples
+ * only. */
 #define XCORR_TILE_DEFAULT 0       /* LDS-DMA depth 4 where allowed, else registers */
 #define XCORR_TILE_DMA8 1          /* buffer loads straight to LDS, 8 steps in flight */
 #define XCORR_TILE_DMA4 2          /* the same, 4 steps in flight                   */
 #define XCORR_TILE_REGS 3          /* loads to registers, byte transposes, LDS writes */
-#define XCORR_TILE_W4 4            /* LDS-DMA, one wave per SIMD owning whole tiles (single plans) */
 
 typedef struct xcorr_plan_s* xcorr_plan_t;
 

@@ -123,21 +123,6 @@ void release(void* ptr)
 
 bool live(xcorr_plan_t p) { return plan_live(p); }
 
-// The four-wave int8 kernel as a one-entry persistent launch.
-hipError_t launch_w4(const LaunchArgs& a, int grid, hipStream_t s)
-{
-    BatchArgs ba;
-    std::memset(&ba, 0, sizeof ba);
-    ba.n_entries = 1;
-    ba.n_blocks = a.n_blocks;
-    ba.xcd_map = a.xcd_map;
-    ba.first[1] = a.n_blocks;
-    ba.e[0] = a;
-    const int per = (a.n_blocks / a.n_items + 7) / 8 * a.n_items;
-    for (int x = 0; x <= 8; ++x) ba.slice[x] = std::min(x * per, a.n_blocks);
-    return launch_i8w4(ba, a.xcd_map ? grid : std::min(grid, a.n_blocks), s);
-}
-
 size_t elem_bytes(const xcorr_plan_desc* d)
 {
     return d->path == XCORR_PATH_I8_MFMA && !(d->flags & XCORR_FLAG_OUT_I32) ? 8 : 4;
@@ -160,15 +145,15 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
                     align);
     if (d->flags & ~(XCORR_FLAG_NO_XCD_MAP | XCORR_FLAG_NO_PERSIST | XCORR_FLAG_OUT_I32))
         return fail(XCORR_ERR_ARG, "unknown flags 0x%x", d->flags);
-    if ((d->flags & XCORR_FLAG_OUT_I32) && (d->path != XCORR_PATH_I8_MFMA || d->tile == kTileW4))
-        return fail(XCORR_ERR_UNSUPPORTED, "int32 output exists for the int8 path (not the W4 tile)");
-    if (d->tile < 0 || d->tile > kTileW4) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
+    if ((d->flags & XCORR_FLAG_OUT_I32) && d->path != XCORR_PATH_I8_MFMA)
+        return fail(XCORR_ERR_UNSUPPORTED, "int32 output exists for the int8 path");
+    if (d->tile < 0 || d->tile > kTileRegs) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
     if (d->tile != kTileDefault && d->path != XCORR_PATH_I8_MFMA)
         return fail(XCORR_ERR_UNSUPPORTED, "tile variants exist for the int8 path only");
-    if ((d->tile == kTileDma8 || d->tile == kTileDma4 || d->tile == kTileW4) && d->n_inputs % 16)
+    if ((d->tile == kTileDma8 || d->tile == kTileDma4) && d->n_inputs % 16)
         return fail(XCORR_ERR_UNSUPPORTED, "LDS-DMA tiles need n_inputs %% 16 == 0");
-    if ((d->tile == kTileDma8 || d->tile == kTileW4) && d->format != XCORR_CI4)
-        return fail(XCORR_ERR_UNSUPPORTED, "the DMA8 and W4 tiles take 4-bit samples");
+    if (d->tile == kTileDma8 && d->format != XCORR_CI4)
+        return fail(XCORR_ERR_UNSUPPORTED, "the DMA8 tile takes 4-bit samples");
     return XCORR_OK;
 }
 
@@ -267,8 +252,7 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
     }
     switch (p->d.path) {
     case XCORR_PATH_I8_MFMA:
-        e = p->tile == kTileW4 ? launch_w4(a, p->persist_grid ? p->persist_grid : 256, p->stream)
-                               : launch_i8(a, p->d.format, p->tile, p->persist_grid, p->d_counters, p->stream);
+        e = launch_i8(a, p->d.format, p->tile, p->persist_grid, p->d_counters, p->stream);
         break;
     case XCORR_PATH_F16_MFMA: e = launch_f16(a, p->d.format, p->stream); break;
     default: e = launch_f32(a, p->d.format, p->stream); break;

@@ -257,7 +257,6 @@ xcorr_status xcorr_batch_create(xcorr_batch_t* out, const xcorr_plan_t* plans, i
     for (int k = 0; k < n_plans; ++k) {
         if (!plan_live(plans[k])) return fail(XCORR_ERR_STATE, "plan %d is not valid", k);
         const xcorr_plan_s* p = plans[k];
-        if (p->tile == kTileW4) return fail(XCORR_ERR_UNSUPPORTED, "the four-wave tile runs single plans only");
         if (p->d.path != XCORR_PATH_I8_MFMA) return fail(XCORR_ERR_UNSUPPORTED, "batches use the int8 path");
         if (fmt >= 0 && p->d.format != fmt) return fail(XCORR_ERR_ARG, "plans of a batch must share the format");
         fmt = p->d.format;

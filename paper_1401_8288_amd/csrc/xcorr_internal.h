@@ -152,7 +152,6 @@ constexpr int kTileDefault = 0;    // LDS-DMA, depth 4, where the shape allows
 constexpr int kTileDma8 = 1;       // LDS-DMA staging, 8 copies in flight
 constexpr int kTileDma4 = 2;       // LDS-DMA staging, 4 copies in flight
 constexpr int kTileRegs = 3;       // register staging (byte transposes + LDS writes)
-constexpr int kTileW4 = 4;         // LDS-DMA, four waves (one per SIMD), whole tiles per wave
 
 // Waves per workgroup of each kernel (the host plans work items to match).
 constexpr int kWavesI8 = 8;
@@ -166,7 +165,6 @@ constexpr int kWavesF32 = 4;
 // queue uses and leaves zero.
 hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, int* counters, hipStream_t s);
 hipError_t launch_i8_batch(const BatchArgs& ba, int fmt, int tile, int grid, hipStream_t s);
-hipError_t launch_i8w4(const BatchArgs& ba, int grid, hipStream_t s);
 hipError_t launch_f16(const LaunchArgs& a, int fmt, hipStream_t s);
 hipError_t launch_f32(const LaunchArgs& a, int fmt, hipStream_t s);
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);

@@ -242,10 +242,10 @@ void plan_items8_paired(int W, std::vector<WorkItem>& items, int& ch_group)
 // shared items make it longer).  (With a static schedule the paired list
 // also made the 2048-input 8-bit window 6 % slower, from L2 misses; with
 // the per-XCD queue it makes it 1 % faster.)
-void plan_items(int path, int tile, int /*fmt*/, int W, std::vector<WorkItem>& items, int& ch_group,
+void plan_items(int path, int /*tile*/, int /*fmt*/, int W, std::vector<WorkItem>& items, int& ch_group,
                 std::vector<WorkItem>& items_src, int& cg_src)
 {
-    const bool i8 = path == XCORR_PATH_I8_MFMA && tile != kTileW4;
+    const bool i8 = path == XCORR_PATH_I8_MFMA;
     if (i8) plan_items8(W, items_src, cg_src);
     else plan_items4(W, items_src, cg_src);
     if (i8 && W > 1) {

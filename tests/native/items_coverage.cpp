@@ -67,7 +67,7 @@ static int check(const char* what, int W, int n_ch, const std::vector<WorkItem>&
 int main()
 {
     const int paths[] = {XCORR_PATH_I8_MFMA, XCORR_PATH_F16_MFMA, XCORR_PATH_F32};
-    const int tiles[] = {kTileDefault, kTileDma8, kTileDma4, kTileRegs, kTileW4};
+    const int tiles[] = {kTileDefault, kTileDma8, kTileDma4, kTileRegs};
     for (int path : paths)
         for (int tile : tiles)
             for (int fmt = 0; fmt < 2; ++fmt)
@@ -81,7 +81,7 @@ int main()
                     }
                     // eight-wave int8 items: at most 10 blocks a wave (two waves
                     // share a SIMD's registers); four-wave items: whole tiles
-                    const int cap = path == XCORR_PATH_I8_MFMA && tile != kTileW4 ? 10 : 16;
+                    const int cap = path == XCORR_PATH_I8_MFMA ? 10 : 16;
                     for (int n_ch = 1; n_ch <= 5; ++n_ch) {
                         if (check("writing table", W, n_ch, items, cg, cap)) return 1;
                         if (check("adding table", W, n_ch, items_src, cg_src, cap)) return 1;

@@ -68,8 +68,8 @@ def _desc(**kw):
     (dict(n_inputs=40000), -6),
     (dict(flags=0x100), -1), (dict(tile=7), -1),
     (dict(tile=1, n_inputs=36), -6),    # LDS-DMA tiles need n_inputs % 16 == 0
-    (dict(tile=1, fmt="ci8"), -6),      # DMA8 and W4 take 4-bit samples only
-    (dict(tile=4, fmt="ci8"), -6),
+    (dict(tile=1, fmt="ci8"), -6),      # DMA8 takes 4-bit samples only
+    (dict(tile=4), -1),
     (dict(tile=3, path="f32"), -6)])    # tile variants exist for the int8 path only
 def test_bad_descriptors_rejected_before_any_device_call(kw, status):
     from paper_1401_8288_amd import xcorr
@@ -215,7 +215,7 @@ def test_int32_output_flag_checks():
     half = xcorr.plan_bytes(512, 64, "ci4", "i8", flags=xcorr.FLAG_OUT_I32)
     nb = 512 * 513 // 2 * 64 * 2
     assert full - half == nb * 4                     # int32 instead of int64 pairs
-    for path, tile in (("f16", 0), ("f32", 0), ("i8", 4)):
+    for path, tile in (("f16", 0), ("f32", 0)):
         with pytest.raises(xcorr.XcorrError) as e:
             xcorr.plan_bytes(512, 64, "ci4", path, flags=xcorr.FLAG_OUT_I32, tile=tile)
         assert e.value.status == -6
