@@ -61,7 +61,7 @@ int64_t row_bytes_of(const xcorr_plan_s* p)
 }
 
 LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
-                      const void* src, void* dst)
+                      const void* src, void* dst, int mode)
 {
     LaunchArgs a;
     a.in = in;
@@ -70,17 +70,90 @@ LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_str
     a.n_inputs = p->d.n_inputs;
     a.t_len = t_len;
     a.n_channels = p->d.n_channels;
-    const bool add = src != nullptr;
-    a.ch_group = add ? p->ch_group_src : p->ch_group;
-    a.n_items = add ? p->n_items_src : p->n_items;
-    a.n_blocks = add ? p->n_items_src * p->n_groups_src : p->n_items * p->n_groups;
+    a.ch_group = p->ch_group;
+    a.n_items = p->n_items;
+    a.n_blocks = p->n_items * p->n_groups;
     a.xcd_map = p->xcd_map;
-    a.out32 = p->out32;
+    a.out32 = mode;
     a.reserved = 0;
-    a.items = add ? p->d_items_src : p->d_items;
+    a.items = p->d_items;
     a.src = src;
     a.dst = dst;
     return a;
+}
+
+AccState acc_state(const xcorr_plan_s* p)
+{
+    return AccState{p->acc_valid, p->acc32_valid, p->samples32};
+}
+
+void set_acc_state(xcorr_plan_s* p, const AccState& s)
+{
+    p->acc_valid = s.acc_valid;
+    p->acc32_valid = s.acc32_valid;
+    p->samples32 = s.samples32;
+}
+
+void reset_acc(xcorr_plan_s* p)
+{
+    set_acc_state(p, AccState{false, false, 0});
+}
+
+ChunkTarget chunk_target(const xcorr_plan_s* p, AccState& s, int64_t len, void* final_dst)
+{
+    ChunkTarget t{nullptr, nullptr, p->out32, false, false};
+    if (!p->acc32) {
+        // fp paths and int32-output plans: the accumulator has the result's type
+        t.src = s.acc_valid ? p->acc : nullptr;
+        t.dst = final_dst ? final_dst : p->acc;
+        if (!final_dst) s.acc_valid = true;
+        return t;
+    }
+    if (final_dst) {
+        t.dst = final_dst;
+        if (s.acc_valid) {
+            if (s.acc32_valid) {
+                t.fold = true;
+                t.fold_acc_valid = true;
+                s.acc32_valid = false;
+                s.samples32 = 0;
+            }
+            t.src = p->acc;
+            t.mode = 0;
+        } else if (s.acc32_valid) {
+            t.src = p->acc32;
+            t.mode = 2;
+        } else {
+            t.mode = 0;
+        }
+        return t;
+    }
+    if (s.acc32_valid && s.samples32 + len > p->acc32_bound) {
+        t.fold = true;
+        t.fold_acc_valid = s.acc_valid;
+        s.acc_valid = true;
+        s.acc32_valid = false;
+        s.samples32 = 0;
+    }
+    t.src = s.acc32_valid ? p->acc32 : nullptr;
+    t.dst = p->acc32;
+    t.mode = 1;
+    s.acc32_valid = true;
+    s.samples32 += len;
+    return t;
+}
+
+hipError_t fold_acc32(const xcorr_plan_s* p, bool acc_valid, hipStream_t stream)
+{
+    return launch_add_i32(p->acc, acc_valid ? p->acc : nullptr, p->acc32, (size_t)p->n_b * p->d.n_channels, stream);
+}
+
+hipError_t launch_dump_of(const xcorr_plan_s* p, void* out, hipStream_t stream)
+{
+    if (p->acc32 && p->acc32_valid)
+        return launch_add_i32(out, p->acc_valid ? p->acc : nullptr, p->acc32, (size_t)p->n_b * p->d.n_channels,
+                              stream);
+    return p->acc_valid ? launch_copy(out, p->acc, p->out_bytes, stream) : launch_fill_zero(out, p->out_bytes, stream);
 }
 
 int64_t fold_bound_of(const xcorr_plan_desc* d)
@@ -157,10 +230,17 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
     return XCORR_OK;
 }
 
+// int64 plans of the int8 path hold an int32 accumulator beside the int64 one.
+bool has_acc32(const xcorr_plan_desc* d)
+{
+    return d->path == XCORR_PATH_I8_MFMA && !(d->flags & XCORR_FLAG_OUT_I32);
+}
+
 size_t plan_device_bytes(const xcorr_plan_desc* d, size_t n_items)
 {
     const int64_t n_b = (int64_t)d->n_inputs * (d->n_inputs + 1) / 2;
-    return (size_t)n_b * d->n_channels * 2 * elem_bytes(d) + n_items * sizeof(WorkItem) + 256 + 32;
+    const size_t acc = (size_t)n_b * d->n_channels * 2 * elem_bytes(d);
+    return acc + (has_acc32(d) ? acc / 2 : 0) + n_items * sizeof(WorkItem) + 256 + 32;
 }
 
 void release_side(xcorr_plan_t p)
@@ -174,9 +254,9 @@ void release_side(xcorr_plan_t p)
 }
 
 xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
-                          const void* src, void* dst)
+                          const void* src, void* dst, int mode)
 {
-    LaunchArgs a = chunk_args(p, in, chan_stride, t_len, src, dst);
+    LaunchArgs a = chunk_args(p, in, chan_stride, t_len, src, dst, mode);
     hipError_t e;
     if (p->d.path == XCORR_PATH_I8_MFMA && p->d.format == XCORR_CI8 && p->tile != kTileRegs &&
         p->d.n_inputs % 16 == 0) {
@@ -203,7 +283,7 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
         // enough channels, split the channels into groups and run the split
         // of every group on a side stream, so that the kernel of group g
         // runs while the later groups are being split.
-        const int cg = p->ch_group_src > p->ch_group ? p->ch_group_src : p->ch_group;
+        const int cg = p->ch_group;
         const int n_ch = p->d.n_channels;
         bool overlap = n_ch >= 4 * kPlaneGroups * cg;
         if (overlap && !p->side) {
@@ -219,7 +299,7 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
         if (!overlap) {
             e = launch_ci8_planes(in, chan_stride, p->d.n_inputs, t_len, n_ch, p->d_planes, p->stream);
             if (e != hipSuccess) return hip_fail(e, "8-bit plane split");
-            a = chunk_args(p, p->d_planes, row * t_len, t_len, src, dst);
+            a = chunk_args(p, p->d_planes, row * t_len, t_len, src, dst, mode);
         } else {
             // the side stream starts after everything before this chunk on
             // the plan's stream (the previous chunk's kernels read d_planes)
@@ -234,14 +314,16 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
                 if (e == hipSuccess) e = hipEventRecord(p->side_ev[g], p->side);
             }
             if (e != hipSuccess) return hip_fail(e, "8-bit plane split");
-            const int64_t out_ch = p->n_b * 2 * elem_bytes(&p->d);    // bytes per channel of the result
+            // bytes per channel of the result and of the source it adds
+            const int64_t out_ch = p->n_b * 2 * (mode == 1 ? 4 : 8);
+            const int64_t src_ch = p->n_b * 2 * (mode == 0 ? 8 : 4);
             for (int g = 0; g < kPlaneGroups; ++g) {
                 e = hipStreamWaitEvent(p->stream, p->side_ev[g], 0);
                 if (e != hipSuccess) return hip_fail(e, "8-bit plane split: stream wait");
                 const int c0 = c_at[g], nc = c_at[g + 1] - c_at[g];
                 LaunchArgs ag = chunk_args(p, p->d_planes + c0 * row * t_len, row * t_len, t_len,
-                                           src ? (const uint8_t*)src + c0 * out_ch : nullptr,
-                                           (uint8_t*)dst + c0 * out_ch);
+                                           src ? (const uint8_t*)src + c0 * src_ch : nullptr,
+                                           (uint8_t*)dst + c0 * out_ch, mode);
                 ag.n_channels = nc;
                 ag.n_blocks = ag.n_items * ((nc + ag.ch_group - 1) / ag.ch_group);
                 e = launch_i8(ag, p->d.format, p->tile, p->persist_grid, p->d_counters, p->stream);
@@ -272,14 +354,18 @@ xcorr_status xcorr::run_window_strided(xcorr_plan_t p, const uint8_t* in, int64_
                                        int64_t n_time, void* final_dst)
 {
     const int64_t row = row_bytes_of(p);
+    AccState st = acc_state(p);
     for (int64_t t0 = 0; t0 < n_time; t0 += p->fold_bound) {
         const int64_t len = std::min<int64_t>(p->fold_bound, n_time - t0);
         const bool last = t0 + len >= n_time;
-        void* dst = (last && final_dst) ? final_dst : p->acc;
-        const void* src = p->acc_valid ? p->acc : nullptr;
-        xcorr_status s = launch_chunk(p, in + t0 * row, chan_stride, (int32_t)len, src, dst);
+        const ChunkTarget t = chunk_target(p, st, len, last ? final_dst : nullptr);
+        if (t.fold) {
+            hipError_t e = fold_acc32(p, t.fold_acc_valid, p->stream);
+            if (e != hipSuccess) return hip_fail(e, "int32 accumulator fold");
+        }
+        xcorr_status s = launch_chunk(p, in + t0 * row, chan_stride, (int32_t)len, t.src, t.dst, t.mode);
         if (s != XCORR_OK) return s;
-        if (dst == p->acc) p->acc_valid = true;
+        set_acc_state(p, st);
     }
     return XCORR_OK;
 }
@@ -308,11 +394,10 @@ xcorr_status xcorr_plan_bytes(const xcorr_plan_desc* d, size_t* bytes)
     xcorr_status s = check_desc(d);
     if (s != XCORR_OK) return s;
     if (!bytes) return fail(XCORR_ERR_ARG, "null output");
-    std::vector<WorkItem> items, items_src;
-    int cg, cg_src;
-    plan_items(d->path, d->tile, d->format, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, cg, items_src,
-               cg_src);
-    *bytes = plan_device_bytes(d, stored_items(items, cg, items_src, cg_src));
+    std::vector<WorkItem> items;
+    int cg;
+    plan_items(d->path, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, cg);
+    *bytes = plan_device_bytes(d, items.size());
     return XCORR_OK;
 }
 
@@ -344,28 +429,30 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
     const int n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     p->persist_grid = (d->flags & XCORR_FLAG_NO_PERSIST) ? 0 : (n_cu + 7) / 8 * 8;
     p->fold_bound = fold_bound_of(d);
+    // the int32 accumulator holds true sums (not the kernel's scaled
+    // partials): at most 2 * 8 * 8 = 128 per sample for 4-bit samples and
+    // 2 * 128 * 128 for 8-bit samples in magnitude
+    p->acc32_bound = d->format == XCORR_CI4 ? 16777215 : 65535;
 
     p->tile = d->tile;
     std::vector<WorkItem>& items = p->h_items;
-    plan_items(d->path, d->tile, d->format, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, p->ch_group,
-               p->h_items_src, p->ch_group_src);
+    plan_items(d->path, (d->n_inputs + kRowBlock - 1) / kRowBlock, items, p->ch_group);
     p->n_items = (int)items.size();
     p->n_groups = (d->n_channels + p->ch_group - 1) / p->ch_group;
-    p->n_items_src = (int)p->h_items_src.size();
-    p->n_groups_src = (d->n_channels + p->ch_group_src - 1) / p->ch_group_src;
-    p->n_items_stored = stored_items(items, p->ch_group, p->h_items_src, p->ch_group_src);
-    const int64_t blocks = std::max((int64_t)p->n_items * p->n_groups, (int64_t)p->n_items_src * p->n_groups_src);
+    const int64_t blocks = (int64_t)p->n_items * p->n_groups;
     if (blocks > (int64_t)1 << 30) {
         delete p;
         return fail(XCORR_ERR_UNSUPPORTED, "too many work items");
     }
 
     e = hipMalloc(&p->acc, p->out_bytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, p->n_items_stored * sizeof(WorkItem));
+    if (e == hipSuccess && has_acc32(d)) e = hipMalloc(&p->acc32, p->out_bytes / 2);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, items.size() * sizeof(WorkItem));
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_counters, kCounterInts * sizeof(int));
     if (e == hipSuccess) e = hipMemset(p->d_counters, 0, kCounterInts * sizeof(int));
     if (e != hipSuccess) {
         release(p->acc);
+        release(p->acc32);
         release(p->d_items);
         release(p->d_counters);
         delete p;
@@ -374,14 +461,9 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
                     "plan allocation: %s", hipGetErrorString(e));
     }
     e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
-    p->d_items_src = p->d_items;
-    if (e == hipSuccess && p->n_items_stored > items.size()) {
-        p->d_items_src = p->d_items + items.size();
-        e = hipMemcpy(p->d_items_src, p->h_items_src.data(), p->h_items_src.size() * sizeof(WorkItem),
-                      hipMemcpyHostToDevice);
-    }
     if (e != hipSuccess) {
         release(p->acc);
+        release(p->acc32);
         release(p->d_items);
         release(p->d_counters);
         delete p;
@@ -415,13 +497,12 @@ xcorr_status xcorr_dump(xcorr_plan_t p, void* d_out, int reset, xcorr_dump_info*
     if (!live(p)) return fail(XCORR_ERR_STATE, "invalid plan handle");
     xcorr_status s = check_ptr(d_out, "d_out");
     if (s != XCORR_OK) return s;
-    hipError_t e = p->acc_valid ? launch_copy(d_out, p->acc, p->out_bytes, p->stream)
-                                : launch_fill_zero(d_out, p->out_bytes, p->stream);
+    hipError_t e = launch_dump_of(p, d_out, p->stream);
     if (e != hipSuccess) return hip_fail(e, "dump");
     p->n_dumps += 1;
     fill_info(p, info);
     if (reset) {
-        p->acc_valid = false;
+        reset_acc(p);
         p->samples = 0;
         p->window_start = p->total;
     }
@@ -443,11 +524,11 @@ xcorr_status xcorr_accumulate_dump(xcorr_plan_t p, const void* d_in, int64_t n_t
         // the last launch writes the dump directly; the accumulator restarts
         s = run_window(p, d_in, n_time, d_out);
         if (s != XCORR_OK) return s;
-        p->acc_valid = false;
+        reset_acc(p);
     } else {
         s = run_window(p, d_in, n_time, nullptr);
         if (s != XCORR_OK) return s;
-        hipError_t e = launch_copy(d_out, p->acc, p->out_bytes, p->stream);
+        hipError_t e = launch_dump_of(p, d_out, p->stream);
         if (e != hipSuccess) return hip_fail(e, "dump copy");
     }
     p->samples += n_time;
@@ -465,7 +546,7 @@ xcorr_status xcorr_query(xcorr_plan_t p, xcorr_plan_info* info)
 {
     if (!live(p)) return fail(XCORR_ERR_STATE, "invalid plan handle");
     if (!info) return fail(XCORR_ERR_ARG, "null info");
-    info->device_bytes = plan_device_bytes(&p->d, p->n_items_stored);
+    info->device_bytes = plan_device_bytes(&p->d, p->h_items.size());
     info->output_bytes = p->out_bytes;
     info->input_bytes_per_sample =
         (size_t)p->d.n_inputs * (p->d.format == XCORR_CI4 ? 1 : 2) * p->d.n_channels;
@@ -495,7 +576,8 @@ xcorr_status xcorr_dump_tiles(xcorr_plan_t p, void* d_out, const uint8_t* tile_s
     }
     e = hipMemcpyAsync(p->d_tile_sel, tile_select, nsel, hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess)
-        e = launch_dump_tiles(d_out, p->acc, p->acc_valid ? 1 : 0, p->d_tile_sel, p->d.n_inputs, p->d.n_channels,
+        e = launch_dump_tiles(d_out, p->acc, p->acc_valid ? 1 : 0, p->acc32_valid ? p->acc32 : nullptr,
+                              p->d_tile_sel, p->d.n_inputs, p->d.n_channels,
                               (int)(2 * elem_bytes(&p->d)), reset ? 1 : 0, p->stream);
     if (e != hipSuccess) return hip_fail(e, "tile dump");
     p->n_dumps += 1;
@@ -623,6 +705,7 @@ xcorr_status xcorr_destroy(xcorr_plan_t p)
     }
     hipError_t e = hipStreamSynchronize(p->stream);
     release(p->acc);
+    release(p->acc32);
     release(p->d_items);
     release(p->d_counters);
     release(p->d_tile_sel);

@@ -49,6 +49,22 @@ __global__ void __launch_bounds__(256) ci8_planes_kernel(const uint8_t* in, int6
     }
 }
 
+// out[k] = (a64 ? a64[k] : 0) + (a32 ? a32[k] : 0) over n (re, im) pairs, out
+// and a64 int64, a32 int32 (out may be a64).
+__global__ void __launch_bounds__(256) add_i32_kernel(longlong2* out, const longlong2* a64, const int2* a32, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        longlong2 v = a64 ? a64[k] : longlong2{0, 0};
+        if (a32) {
+            const int2 w = a32[k];
+            v.x += w.x;
+            v.y += w.y;
+        }
+        out[k] = v;
+    }
+}
+
 int grid_for(size_t n)
 {
     const size_t b = (n + 255) / 256;
@@ -71,6 +87,13 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
     hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n16)), dim3(256), 0, s, (v4i*)dst,
                        (const v4i*)src, n16, (uint8_t*)dst + n16 * 16,
                        (const uint8_t*)src + n16 * 16, n_tail);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_i32(void* out, const void* a64, const void* a32, size_t n_pairs, hipStream_t s)
+{
+    hipLaunchKernelGGL(add_i32_kernel, dim3(grid_for(n_pairs)), dim3(256), 0, s, (longlong2*)out,
+                       (const longlong2*)a64, (const int2*)a32, n_pairs);
     return hipGetLastError();
 }
 

@@ -72,8 +72,7 @@ void make_slices(const std::vector<Entry>& es, const int* first, int n_blocks, i
     double total = 0;
     for (size_t e = 0; e < es.size(); ++e) {
         const xcorr_plan_s* p = es[e].plan;
-        const bool add = es[e].a.items != p->d_items;          // the table of adding launches
-        const std::vector<WorkItem>& its = add ? p->h_items_src : p->h_items;
+        const std::vector<WorkItem>& its = p->h_items;
         const int n_items = es[e].a.n_items;
         double gc = 0;
         for (const WorkItem& it : its) gc += item_blocks(it);
@@ -95,14 +94,18 @@ void make_slices(const std::vector<Entry>& es, const int* first, int n_blocks, i
 
 xcorr_status launch_entries_same_width(xcorr_batch_t b, const std::vector<Entry>& es, const xcorr_batch_config& cfg);
 
-// Entries of both output widths go out as one launch per width.
+// Entries of different result modes (LaunchArgs.out32) go out as one
+// launch per mode.
 xcorr_status launch_entries(xcorr_batch_t b, const std::vector<Entry>& es, const xcorr_batch_config& cfg)
 {
-    std::vector<Entry> w64, w32;
-    for (const Entry& e : es) (e.a.out32 ? w32 : w64).push_back(e);
-    xcorr_status s = w64.empty() ? XCORR_OK : launch_entries_same_width(b, w64, cfg);
-    if (s == XCORR_OK && !w32.empty()) s = launch_entries_same_width(b, w32, cfg);
-    return s;
+    std::vector<Entry> by_mode[3];
+    for (const Entry& e : es) by_mode[e.a.out32].push_back(e);
+    for (int m = 0; m < 3; ++m) {
+        if (by_mode[m].empty()) continue;
+        xcorr_status s = launch_entries_same_width(b, by_mode[m], cfg);
+        if (s != XCORR_OK) return s;
+    }
+    return XCORR_OK;
 }
 
 xcorr_status launch_entries_same_width(xcorr_batch_t b, const std::vector<Entry>& es, const xcorr_batch_config& cfg)
@@ -144,8 +147,10 @@ xcorr_status run_step(xcorr_batch_t b, const void* const* d_in, const int64_t* n
         chunks[k] = n_time[k] > 0 ? (n_time[k] + p->fold_bound - 1) / p->fold_bound : 0;
         rounds = std::max(rounds, chunks[k]);
     }
-    std::vector<char> valid(np);
-    for (size_t k = 0; k < np; ++k) valid[k] = fused_to_acc ? 0 : b->plans[k]->acc_valid;
+    // fused_to_acc: every chunk writes (the first) or adds to the plan's own
+    // accumulator in its result type, from an empty state
+    std::vector<AccState> st(np);
+    for (size_t k = 0; k < np; ++k) st[k] = fused_to_acc ? AccState{false, false, 0} : acc_state(b->plans[k]);
     for (int64_t r = 0; r < rounds; ++r) {
         std::vector<Entry> es;
         for (size_t k = 0; k < np; ++k) {
@@ -155,15 +160,26 @@ xcorr_status run_step(xcorr_batch_t b, const void* const* d_in, const int64_t* n
             const int64_t t0 = r * p->fold_bound;
             const int64_t len = std::min<int64_t>(p->fold_bound, n_time[k] - t0);
             const bool last = r == chunks[k] - 1;
-            void* dst = p->acc;
-            if (last && !fused_to_acc && d_out[k] && reset && reset[k]) dst = d_out[k];
-            const void* src = valid[k] ? p->acc : nullptr;
+            ChunkTarget t;
+            if (fused_to_acc) {
+                t = ChunkTarget{st[k].acc_valid ? p->acc : nullptr, p->acc, p->out32, false, false};
+                st[k].acc_valid = true;
+            } else {
+                void* fin = (last && d_out[k] && reset && reset[k]) ? d_out[k] : nullptr;
+                t = chunk_target(p, st[k], len, fin);
+            }
+            if (t.fold) {
+                // the plan's int32 accumulator is full: fold it first (its
+                // own launch; windows past the fold bound only)
+                hipError_t e = fold_acc32(p, t.fold_acc_valid, b->stream);
+                if (e != hipSuccess) return hip_fail(e, "int32 accumulator fold");
+            }
             Entry en;
-            en.a = chunk_args(p, (const uint8_t*)d_in[k] + t0 * row, row * n_time[k], (int32_t)len, src, dst);
+            en.a = chunk_args(p, (const uint8_t*)d_in[k] + t0 * row, row * n_time[k], (int32_t)len, t.src, t.dst,
+                              t.mode);
             en.t_len = len;
             en.plan = p;
             es.push_back(en);
-            if (dst == p->acc) valid[k] = 1;
         }
         xcorr_status s = launch_entries(b, es, cfg);
         if (s != XCORR_OK) return s;
@@ -175,12 +191,11 @@ xcorr_status run_step(xcorr_batch_t b, const void* const* d_in, const int64_t* n
         const bool dump = d_out[k] != nullptr;
         const bool rst = dump && reset && reset[k];
         const bool fused = dump && rst && n_time[k] > 0;
+        set_acc_state(p, st[k]);
         if (dump && !fused) {
-            hipError_t e = valid[k] ? launch_copy(d_out[k], p->acc, p->out_bytes, b->stream)
-                                    : launch_fill_zero(d_out[k], p->out_bytes, b->stream);
+            hipError_t e = launch_dump_of(p, d_out[k], b->stream);
             if (e != hipSuccess) return hip_fail(e, "batch dump");
         }
-        p->acc_valid = fused ? false : (bool)valid[k];
         p->samples += n_time[k];
         p->total += n_time[k];
         if (dump) {
@@ -188,7 +203,7 @@ xcorr_status run_step(xcorr_batch_t b, const void* const* d_in, const int64_t* n
             if (info) fill_info(p, &info[k]);
         }
         if (rst) {
-            p->acc_valid = false;
+            reset_acc(p);
             p->samples = 0;
             p->window_start = p->total;
         }
@@ -334,7 +349,7 @@ xcorr_status xcorr_batch_autotune(xcorr_batch_t b, const void* const* d_in, cons
     xcorr_status s = check_step(b, d_in, n_time, nullptr);
     if (s != XCORR_OK) return s;
     for (xcorr_plan_t p : b->plans)
-        if (p->acc_valid || p->samples != 0)
+        if (p->acc_valid || p->acc32_valid || p->samples != 0)
             return fail(XCORR_ERR_STATE, "autotune needs every plan freshly reset");
     std::vector<int> tiles;
     if (b->dma_ok) tiles = {kTileDma4, kTileDma8, kTileRegs};
@@ -391,7 +406,8 @@ xcorr_status xcorr_batch_capture(xcorr_batch_t b, const void* const* d_in, const
     const size_t np = b->plans.size();
     for (size_t k = 0; k < np; ++k) {
         if (n_time[k] <= 0 || !d_out[k]) return fail(XCORR_ERR_ARG, "a graph step needs n_time > 0 and d_out for every plan");
-        if (b->plans[k]->acc_valid) return fail(XCORR_ERR_STATE, "graph capture needs every plan freshly reset");
+        if (b->plans[k]->acc_valid || b->plans[k]->acc32_valid)
+            return fail(XCORR_ERR_STATE, "graph capture needs every plan freshly reset");
     }
     if (!b->stream) return fail(XCORR_ERR_ARG, "graph capture needs a non-null batch stream");
     xcorr_graph_t g = new (std::nothrow) xcorr_graph_s();
@@ -445,7 +461,7 @@ xcorr_status xcorr_graph_launch(xcorr_graph_t g)
         p->n_dumps += 1;
         p->samples = 0;
         p->window_start = p->total;
-        p->acc_valid = false;
+        reset_acc(p);
     }
     return XCORR_OK;
 }

@@ -19,20 +19,20 @@ struct xcorr_plan_s {
     size_t out_bytes = 0;
     void* acc = nullptr;            // accumulator, same layout as a dump
     bool acc_valid = false;         // false: accumulator is logically zero
+    // int64 plans of the int8 path: launches that add to the integration
+    // add into this int32 accumulator ([channel][tri][2] int32) instead of
+    // reading and writing the int64 one; it is folded into acc (int64)
+    // before it would hold more than fold_bound samples, and a dump adds
+    // the two.  The integration is acc (if valid) + acc32 (if valid).
+    void* acc32 = nullptr;
+    bool acc32_valid = false;       // false: acc32 is logically zero
+    int64_t samples32 = 0;          // samples summed in acc32 since its last fold
+    int64_t acc32_bound = 0;        // most samples acc32 holds exactly
     xcorr::WorkItem* d_items = nullptr;
     std::vector<xcorr::WorkItem> h_items;
     int n_items = 0;                // items per channel group
     int ch_group = 1;
     int n_groups = 0;
-    // Launches that add to an accumulator (src != null) use a second table:
-    // one channel per item, since the paired diagonal items of 4-bit plans
-    // make those launches slower.  Equal to the first when nothing is paired.
-    xcorr::WorkItem* d_items_src = nullptr;   // inside the d_items allocation
-    std::vector<xcorr::WorkItem> h_items_src;
-    int n_items_src = 0;
-    int ch_group_src = 1;
-    int n_groups_src = 0;
-    size_t n_items_stored = 0;      // items in the d_items allocation
     int xcd_map = 1;
     int out32 = 0;                  // int32 (re, im) output (XCORR_FLAG_OUT_I32)
     int tile = 0;                   // int8 tile variant in use
@@ -63,7 +63,32 @@ xcorr_status check_ptr(const void* ptr, const char* name);
 int64_t row_bytes_of(const xcorr_plan_s* p);
 // Launch arguments of one time chunk of a plan.
 LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
-                      const void* src, void* dst);
+                      const void* src, void* dst, int mode);
+// The accumulators' state while the launches of a call are planned.
+struct AccState {
+    bool acc_valid, acc32_valid;
+    int64_t samples32;
+};
+AccState acc_state(const xcorr_plan_s* p);
+void set_acc_state(xcorr_plan_s* p, const AccState& s);
+// Where one time chunk of len samples goes: the source its launch adds
+// (null: none), its destination and its result mode (LaunchArgs.out32).
+// final_dst: the chunk is the last of a fused dump and writes the dump
+// there.  fold: the int32 accumulator must first be folded into the int64
+// one (fold_acc32 with fold_acc_valid).  Updates s as if the launch ran.
+struct ChunkTarget {
+    const void* src;
+    void* dst;
+    int mode;
+    bool fold, fold_acc_valid;
+};
+ChunkTarget chunk_target(const xcorr_plan_s* p, AccState& s, int64_t len, void* final_dst);
+// acc = (acc_valid ? acc : 0) + acc32, enqueued on stream.
+hipError_t fold_acc32(const xcorr_plan_s* p, bool acc_valid, hipStream_t stream);
+// Writes the plan's integration (both accumulators, per its state) to out.
+hipError_t launch_dump_of(const xcorr_plan_s* p, void* out, hipStream_t stream);
+// Marks the integration empty (a dump with reset).
+void reset_acc(xcorr_plan_s* p);
 void fill_info(const xcorr_plan_s* p, xcorr_dump_info* info);
 // XCORR_ERR_ARG if adding n_time samples would take an int32-output plan's
 // window past its fold bound.
@@ -78,13 +103,9 @@ xcorr_status run_window_strided(xcorr_plan_s* p, const uint8_t* in, int64_t chan
                                 void* final_dst);
 // Relative cost of a work item (MFMA blocks its waves own).
 int item_blocks(const WorkItem& it);
-// Work items of a plan (xcorr_items.cpp): items / ch_group for launches that
-// write their result, items_src / cg_src for launches that add to an
-// accumulator; W row blocks of 64 inputs.
-void plan_items(int path, int tile, int fmt, int W, std::vector<WorkItem>& items, int& ch_group,
-                std::vector<WorkItem>& items_src, int& cg_src);
-// Items a plan's device table holds for those two lists.
-size_t stored_items(const std::vector<WorkItem>& items, int cg, const std::vector<WorkItem>& items_src, int cg_src);
+// Work items of a plan (xcorr_items.cpp) for W row blocks of 64 inputs:
+// items per group of ch_group channels.
+void plan_items(int path, int W, std::vector<WorkItem>& items, int& ch_group);
 // One fused window (accumulate + dump with reset) for each plan, all in one
 // persistent launch per time chunk.  The plans must share the format.
 xcorr_status run_fused_windows(hipStream_t stream, int* d_counters, const xcorr_batch_config& cfg,

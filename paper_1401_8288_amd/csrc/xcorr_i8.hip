@@ -723,13 +723,17 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
     const int64_t nb = (int64_t)a.n_inputs * (a.n_inputs + 1) / 2;
     // Launches that add to a result (src, the plan's accumulator or the
     // previous chunk's output) read it here.  src may be dst, so the
-    // compiler cannot move a load above an earlier store: the four loads of
-    // a block are written before its stores and, in the LDS-DMA variants,
-    // before the stores of the block ahead of it, so the wave waits for one
-    // memory round trip per item (per block in the register-staged
-    // variants, which have no registers to spare) instead of one per row.
-    typedef typename std::conditional<O32 != 0, int2, longlong2>::type Pair;
-    const Pair* src = (const Pair*)a.src;
+    // compiler cannot move a load above an earlier store: in the LDS-DMA
+    // variants an int32 source is loaded whole before the first store, and
+    // an int64 one block by block ahead of the stores of the block before
+    // it, so the wave waits for about one memory round trip per item (per
+    // block in the register-staged variants, which have no registers to
+    // spare) instead of one per row.
+    // result mode OM: 0 int64 (re, im) adding int64, 1 int32 adding int32,
+    // 2 int64 adding int32 (an int32 accumulator's last launch into a dump)
+    typedef typename std::conditional<O32 == 1, int2, longlong2>::type Pair;
+    typedef typename std::conditional<O32 == 0, longlong2, int2>::type SrcPair;
+    const SrcPair* src = (const SrcPair*)a.src;
     Pair* dst = (Pair*)a.dst;
     const int jl = lane & 15, il = 4 * (lane >> 4);
     auto pair_index = [&](int n, int r, bool& ok) -> int64_t {
@@ -737,7 +741,7 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
         ok = i < a.n_inputs && j <= i;
         return (int64_t)ch * nb + (int64_t)i * (i + 1) / 2 + j;
     };
-    auto load_block = [&](int n, Pair (&v)[4]) {
+    auto load_block = [&](int n, SrcPair (&v)[4]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             bool ok;
@@ -764,7 +768,31 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
         }
         return;
     }
-    Pair cur[4], nxt[4];
+    if constexpr (O32 != 0 && is_dma(FMT)) {
+        // int32 sources (2 registers a row): every block's source is loaded
+        // before the first store, one memory round trip per item
+        SrcPair all[16][4];
+#pragma unroll
+        for (int n = 0; n < 16; ++n)
+            if (block_on(KIND, n >> 2, n & 3)) load_block(n, all[n]);
+#pragma unroll
+        for (int n = 0; n < 16; ++n) {
+            if (!block_on(KIND, n >> 2, n & 3)) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                bool ok;
+                const int64_t q = pair_index(n, r, ok);
+                if (!ok) continue;
+                Pair o;
+                o.x = (((int64_t)c.re[n >> 2][n & 3][r]) >> shift) + (int64_t)all[n][r].x;
+                o.y = (((int64_t)c.ba[n >> 2][n & 3][r] - (int64_t)c.ab[n >> 2][n & 3][r]) >> shift) +
+                      (int64_t)all[n][r].y;
+                dst[q] = o;
+            }
+        }
+        return;
+    }
+    SrcPair cur[4], nxt[4];
     constexpr bool ahead = is_dma(FMT);
     if (ahead) load_block(next_block<KIND>(-1), nxt);
 #pragma unroll
@@ -822,10 +850,6 @@ __device__ __forceinline__ void dispatch_kind(const LaunchArgs& a, const WaveJob
     case KIND_DIAG_A: run_tile<FMT, KIND_DIAG_A, O32>(a, w, lane, L, st, next, issue_prologue); break;
     case KIND_DIAG_B: run_tile<FMT, KIND_DIAG_B, O32>(a, w, lane, L, st, next, issue_prologue); break;
     case KIND_DIAG:   run_tile<FMT, KIND_DIAG, O32>(a, w, lane, L, st, next, issue_prologue); break;
-    case KIND_QUART0: run_tile<FMT, KIND_QUART0, O32>(a, w, lane, L, st, next, issue_prologue); break;
-    case KIND_QUART1: run_tile<FMT, KIND_QUART1, O32>(a, w, lane, L, st, next, issue_prologue); break;
-    case KIND_QUART2: run_tile<FMT, KIND_QUART2, O32>(a, w, lane, L, st, next, issue_prologue); break;
-    case KIND_QUART3: run_tile<FMT, KIND_QUART3, O32>(a, w, lane, L, st, next, issue_prologue); break;
     default:          run_tile<FMT, KIND_NONE, O32>(a, w, lane, L, st, next, issue_prologue); break;
     }
 }
@@ -977,23 +1001,27 @@ template <int FMT>
 hipError_t launch_variant(const LaunchArgs& a, hipStream_t s)
 {
     const dim3 grid(launch_blocks(a.n_blocks, a.xcd_map)), block(kThreads);
-    if (a.out32) hipLaunchKernelGGL((xcorr_i8_kernel<FMT, 1>), grid, block, 0, s, a);
-    else         hipLaunchKernelGGL((xcorr_i8_kernel<FMT, 0>), grid, block, 0, s, a);
+    if (a.out32 == 1)      hipLaunchKernelGGL((xcorr_i8_kernel<FMT, 1>), grid, block, 0, s, a);
+    else if (a.out32 == 2) hipLaunchKernelGGL((xcorr_i8_kernel<FMT, 2>), grid, block, 0, s, a);
+    else                   hipLaunchKernelGGL((xcorr_i8_kernel<FMT, 0>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
-// Every entry of a batched launch has the same output width (the host
-// splits mixed batches).
+// Every entry of a batched launch has the same result mode (the host splits
+// mixed batches).
 template <int FMT>
 hipError_t launch_batch_variant(const BatchArgs& ba, int grid, hipStream_t s)
 {
-    const bool o32 = ba.e[0].out32 != 0;
+    const int om = ba.e[0].out32;
+    const dim3 g(grid), b(kThreads);
     if constexpr (is_dma(FMT)) {
-        if (o32) hipLaunchKernelGGL((xcorr_i8_persist_kernel<FMT, 1>), dim3(grid), dim3(kThreads), 0, s, ba);
-        else     hipLaunchKernelGGL((xcorr_i8_persist_kernel<FMT, 0>), dim3(grid), dim3(kThreads), 0, s, ba);
+        if (om == 1)      hipLaunchKernelGGL((xcorr_i8_persist_kernel<FMT, 1>), g, b, 0, s, ba);
+        else if (om == 2) hipLaunchKernelGGL((xcorr_i8_persist_kernel<FMT, 2>), g, b, 0, s, ba);
+        else              hipLaunchKernelGGL((xcorr_i8_persist_kernel<FMT, 0>), g, b, 0, s, ba);
     } else {
-        if (o32) hipLaunchKernelGGL((xcorr_i8_batch_kernel<FMT, 1>), dim3(grid), dim3(kThreads), 0, s, ba);
-        else     hipLaunchKernelGGL((xcorr_i8_batch_kernel<FMT, 0>), dim3(grid), dim3(kThreads), 0, s, ba);
+        if (om == 1)      hipLaunchKernelGGL((xcorr_i8_batch_kernel<FMT, 1>), g, b, 0, s, ba);
+        else if (om == 2) hipLaunchKernelGGL((xcorr_i8_batch_kernel<FMT, 2>), g, b, 0, s, ba);
+        else              hipLaunchKernelGGL((xcorr_i8_batch_kernel<FMT, 0>), g, b, 0, s, ba);
     }
     return hipGetLastError();
 }

@@ -20,15 +20,13 @@ namespace xcorr {
 //   HALF0/1 the 8 blocks of columns bj 0-1 / 2-3
 //   DIAG_A  (0,0) (1,0) (1,1) (3,2) (3,3)  }  the diagonal tile in two
 //   DIAG_B  (2,0) (2,1) (2,2) (3,0) (3,1)  }  balanced halves of 5 blocks
-//   QUART_k the 4 blocks of column bj = k
 // The four-wave kernels (fp16, fp32) use FULL/DIAG/HALF tiles; the eight-wave
-// int8 kernel uses at most 8 blocks per wave so that its int32 accumulators
+// int8 kernel uses at most 10 blocks per wave so that its int32 accumulators
 // fit two waves per SIMD.
 // ---------------------------------------------------------------------------
 enum TileKind : int8_t {
     KIND_NONE = 0, KIND_FULL = 1, KIND_DIAG = 2, KIND_HALF0 = 3, KIND_HALF1 = 4,
-    KIND_DIAG_A = 5, KIND_DIAG_B = 6, KIND_QUART0 = 7, KIND_QUART1 = 8, KIND_QUART2 = 9,
-    KIND_QUART3 = 10
+    KIND_DIAG_A = 5, KIND_DIAG_B = 6
 };
 
 // Bit 4*bi + bj set <=> block (bi, bj) belongs to the kind.
@@ -40,7 +38,6 @@ __host__ __device__ constexpr uint32_t kind_mask(int kind)
          : kind == KIND_HALF1   ? 0xCCCCu
          : kind == KIND_DIAG_A  ? 0xC031u
          : kind == KIND_DIAG_B  ? 0x3700u
-         : kind >= KIND_QUART0 && kind <= KIND_QUART3 ? (0x1111u << (kind - KIND_QUART0))
          : 0u;
 }
 
@@ -70,7 +67,8 @@ struct LaunchArgs {
     int32_t n_items;               // work items per group
     int32_t n_blocks;              // total work items of the launch
     int32_t xcd_map;               // 1: XCD-aware block -> item mapping
-    int32_t out32;                 // 1: int32 (re, im) results and accumulator, else int64
+    int32_t out32;                 // result mode: 0 int64 (re, im) pairs (src int64); 1 int32 pairs
+                                   // (src int32); 2 int64 pairs added to an int32 src
     int32_t reserved;
     const WorkItem* items;
     const void* src;               // optional accumulator to add (same layout as dst)
@@ -169,6 +167,9 @@ hipError_t launch_f16(const LaunchArgs& a, int fmt, hipStream_t s);
 hipError_t launch_f32(const LaunchArgs& a, int fmt, hipStream_t s);
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// out = a64 + a32 over n_pairs (re, im) pairs: out and a64 int64, a32 int32;
+// either source may be null (zero); out may equal a64.
+hipError_t launch_add_i32(void* out, const void* a64, const void* a32, size_t n_pairs, hipStream_t s);
 // 8-bit samples [channel][time][input][re, im] (channel c at in + c *
 // chan_stride) -> out[channel][time][re of every input, then im of every
 // input] (rows of the same 2 n_inputs bytes); n_inputs % 8 == 0.

@@ -3,7 +3,6 @@
 // uploaded as a table; the kernels read their item by index.
 #include "xcorr_host.h"
 
-#include <cstring>
 
 namespace xcorr {
 
@@ -85,70 +84,23 @@ void plan_items4(int W, std::vector<WorkItem>& items, int& ch_group)
     }
 }
 
-// The same decomposition for eight waves per workgroup (int8 kernel), with at
-// most 8 blocks per wave: every FULL tile becomes two HALF waves, a diagonal
-// tile two balanced DIAG_A / DIAG_B waves of 5 blocks, and the off-diagonal
-// tile inside a diagonal pair four QUART waves of 4 blocks, so a diagonal
-// work item issues 9/16 of the MFMAs of an off-diagonal one per SIMD.
-void plan_items8(int W, std::vector<WorkItem>& items, int& ch_group)
+// Eight waves per workgroup (int8 kernel), one row block per channel: four
+// channels per workgroup, each diagonal tile in two balanced DIAG_A / DIAG_B
+// waves of 5 blocks.
+void plan_items8_single(std::vector<WorkItem>& items, int& ch_group)
 {
     items.clear();
-    if (W == 1) {
-        // one row block per channel: four channels per workgroup
-        ch_group = 4;
-        WorkItem it = blank_item();
-        for (int s = 0; s < kSlots; ++s) {
-            it.rb[s] = 0;
-            it.ch[s] = (int8_t)s;
-            for (int h = 0; h < 2; ++h) {
-                it.wi[2 * s + h] = it.wj[2 * s + h] = (int8_t)s;
-                it.kind[2 * s + h] = h ? KIND_DIAG_B : KIND_DIAG_A;
-            }
-        }
-        items.push_back(it);
-        return;
-    }
-    ch_group = 1;
-    const int SB = (W + 1) / 2;
-    for (int R = 0; R < SB; ++R) {
-        int rr[2], nr = 0;
-        for (int k = 0; k < 2; ++k) if (2 * R + k < W) rr[nr++] = 2 * R + k;
-        for (int S = 0; S <= R; ++S) {
-            WorkItem it = blank_item();
-            int w = 0;
-            auto add = [&](int si, int sj, int kind) {
-                it.wi[w] = (int8_t)si;
-                it.wj[w] = (int8_t)sj;
-                it.kind[w] = (int8_t)kind;
-                ++w;
-            };
-            if (S < R) {
-                int ss[2], ns = 0;
-                for (int k = 0; k < 2; ++k) if (2 * S + k < W) ss[ns++] = 2 * S + k;
-                int slot = 0;
-                for (int k = 0; k < nr; ++k) it.rb[slot++] = (int16_t)rr[k];
-                for (int k = 0; k < ns; ++k) it.rb[slot++] = (int16_t)ss[k];
-                for (int a = 0; a < nr; ++a)
-                    for (int b = 0; b < ns; ++b) {
-                        add(a, nr + b, KIND_HALF0);
-                        add(a, nr + b, KIND_HALF1);
-                    }
-            } else if (nr == 2) {
-                it.rb[0] = (int16_t)rr[0];
-                it.rb[1] = (int16_t)rr[1];
-                for (int q = 0; q < 4; ++q) add(1, 0, KIND_QUART0 + q);
-                add(0, 0, KIND_DIAG_A);
-                add(0, 0, KIND_DIAG_B);
-                add(1, 1, KIND_DIAG_A);
-                add(1, 1, KIND_DIAG_B);
-            } else {
-                it.rb[0] = (int16_t)rr[0];
-                add(0, 0, KIND_DIAG_A);
-                add(0, 0, KIND_DIAG_B);
-            }
-            items.push_back(it);
+    ch_group = 4;
+    WorkItem it = blank_item();
+    for (int s = 0; s < kSlots; ++s) {
+        it.rb[s] = 0;
+        it.ch[s] = (int8_t)s;
+        for (int h = 0; h < 2; ++h) {
+            it.wi[2 * s + h] = it.wj[2 * s + h] = (int8_t)s;
+            it.kind[2 * s + h] = h ? KIND_DIAG_B : KIND_DIAG_A;
         }
     }
+    items.push_back(it);
 }
 
 void plan_items8_paired(int W, std::vector<WorkItem>& items, int& ch_group)
@@ -234,34 +186,19 @@ void plan_items8_paired(int W, std::vector<WorkItem>& items, int& ch_group)
 
 }  // namespace
 
-// Work items of a plan: items / ch_group for launches that write their
-// result (reset, dump), items_src / cg_src for launches that add to an
-// accumulator.  int8 plans pair the diagonal items of two channels in the
-// first table only: pairing made adding launches 6 % slower at the LWA
-// size (their epilogue reads the accumulator, and the 10-block waves of the
-// shared items make it longer).  (With a static schedule the paired list
-// also made the 2048-input 8-bit window 6 % slower, from L2 misses; with
-// the per-XCD queue it makes it 1 % faster.)
-void plan_items(int path, int /*tile*/, int /*fmt*/, int W, std::vector<WorkItem>& items, int& ch_group,
-                std::vector<WorkItem>& items_src, int& cg_src)
+// Work items of a plan, used by every launch.  int8 plans pair the
+// diagonal items of two channels (more than one row block) or put four
+// channels in one item (one row block).  Adding launches take the same
+// table: they add into an int32 accumulator.  (When they read and wrote
+// the int64 accumulator the paired items made them 6 % slower at the LWA
+// size, and a second, single-channel table served them.)  With a static
+// schedule the paired list also made the 2048-input 8-bit window 6 %
+// slower, from L2 misses; with the per-XCD queue it makes it 1 % faster.
+void plan_items(int path, int W, std::vector<WorkItem>& items, int& ch_group)
 {
-    const bool i8 = path == XCORR_PATH_I8_MFMA;
-    if (i8) plan_items8(W, items_src, cg_src);
-    else plan_items4(W, items_src, cg_src);
-    if (i8 && W > 1) {
-        plan_items8_paired(W, items, ch_group);
-    } else {
-        items = items_src;
-        ch_group = cg_src;
-    }
-}
-
-// Items the plan's device table holds: one list, or both when they differ.
-size_t stored_items(const std::vector<WorkItem>& items, int cg, const std::vector<WorkItem>& items_src, int cg_src)
-{
-    const bool same = cg == cg_src && items.size() == items_src.size() &&
-                      std::memcmp(items.data(), items_src.data(), items.size() * sizeof(WorkItem)) == 0;
-    return same ? items.size() : items.size() + items_src.size();
+    if (path != XCORR_PATH_I8_MFMA) plan_items4(W, items, ch_group);
+    else if (W == 1) plan_items8_single(items, ch_group);
+    else plan_items8_paired(W, items, ch_group);
 }
 
 }  // namespace xcorr

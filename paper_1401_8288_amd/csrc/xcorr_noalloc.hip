@@ -72,9 +72,7 @@ const Table& table_for(int W)
     auto it = g_tables.find(W);
     if (it == g_tables.end()) {
         Table t;
-        std::vector<WorkItem> src;
-        int cg_src = 1;
-        plan_items(XCORR_PATH_I8_MFMA, kTileDefault, XCORR_CI4, W, t.items, t.ch_group, src, cg_src);
+        plan_items(XCORR_PATH_I8_MFMA, W, t.items, t.ch_group);
         it = g_tables.emplace(W, std::move(t)).first;
     }
     return it->second;

@@ -1,6 +1,5 @@
 // Host check of the X-stage work-item planner (xcorr_items.cpp): for every
-// path and tile, both item tables, row-block counts 1..24 and channel counts
-// 1..5, every 16x16 block (i >= j) of the lower triangle of every channel is
+// path, row-block counts 1..24 and channel counts 1..5, every 16x16 block (i >= j) of the lower triangle of every channel is
 // computed by exactly one wave, no wave computes a block above the diagonal
 // or outside the channels, each channel's blocks come from tiles of that
 // channel, and a wave of the eight-wave int8 kernel never owns more than 10
@@ -67,26 +66,17 @@ static int check(const char* what, int W, int n_ch, const std::vector<WorkItem>&
 int main()
 {
     const int paths[] = {XCORR_PATH_I8_MFMA, XCORR_PATH_F16_MFMA, XCORR_PATH_F32};
-    const int tiles[] = {kTileDefault, kTileDma8, kTileDma4, kTileRegs};
     for (int path : paths)
-        for (int tile : tiles)
-            for (int fmt = 0; fmt < 2; ++fmt)
-                for (int W = 1; W <= 24; ++W) {
-                    std::vector<WorkItem> items, items_src;
-                    int cg = 0, cg_src = 0;
-                    plan_items(path, tile, fmt, W, items, cg, items_src, cg_src);
-                    if (stored_items(items, cg, items_src, cg_src) < items.size()) {
-                        std::printf("stored_items below the first table\n");
-                        return 1;
-                    }
-                    // eight-wave int8 items: at most 10 blocks a wave (two waves
-                    // share a SIMD's registers); four-wave items: whole tiles
-                    const int cap = path == XCORR_PATH_I8_MFMA ? 10 : 16;
-                    for (int n_ch = 1; n_ch <= 5; ++n_ch) {
-                        if (check("writing table", W, n_ch, items, cg, cap)) return 1;
-                        if (check("adding table", W, n_ch, items_src, cg_src, cap)) return 1;
-                    }
-                }
+        for (int W = 1; W <= 24; ++W) {
+            std::vector<WorkItem> items;
+            int cg = 0;
+            plan_items(path, W, items, cg);
+            // eight-wave int8 items: at most 10 blocks a wave (two waves
+            // share a SIMD's registers); four-wave items: whole tiles
+            const int cap = path == XCORR_PATH_I8_MFMA ? 10 : 16;
+            for (int n_ch = 1; n_ch <= 5; ++n_ch)
+                if (check("items", W, n_ch, items, cg, cap)) return 1;
+        }
     std::printf("ok\n");
     return 0;
 }

@@ -243,6 +243,50 @@ def test_int32_fold_past_two_to_the_31(fmt, re, im, per_sample):
     assert (got[..., 1] == 0).all()
 
 
+@pytest.mark.parametrize("fmt", ["ci4", "ci8"])
+def test_int32_accumulator_folds_across_calls(fmt):
+    # xcorr_accumulate of an int64 plan adds into an int32 accumulator that
+    # is folded into the int64 one before it passes the fold bound: calls of
+    # uneven length that cross the bound several times (within a call and
+    # between calls), dumps without reset in between, a tile dump with
+    # restart, then a fused accumulate_dump; worst-case constant samples
+    # make every int32 partial reach its limit
+    say("int32 accumulator folds", fmt)
+    X = xc()
+    lo = -8 if fmt == "ci4" else -128
+    n_in, n_ch = 72, 3
+    lens = [40000, 30000, 70000, 1, 65535, 20000]
+    xs = [synth.constant_input(n_ch, n, n_in, fmt, lo, lo, device=DEV) if k % 2 == 0 else
+          synth.random_input(n_ch, n, n_in, fmt, seed=300 + k, device=DEV) for k, n in enumerate(lens)]
+    refs = [oracle.correlate(x.cpu().numpy(), fmt) for x in xs]
+    p = X.Plan(n_in, n_ch, fmt, "i8")
+    total = np.zeros_like(refs[0])
+    for k, (x, r) in enumerate(zip(xs[:-1], refs[:-1])):
+        p.accumulate(x)
+        total = total + r
+        if k in (1, 3):
+            out, info = p.dump(reset=False)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(out.cpu().numpy(), total, err_msg="dump after call %d" % k)
+            assert info.samples_accumulated == sum(lens[:k + 1])
+    # restart tile (1, 0) only: its baselines start again from zero
+    sel = [0, 1, 0]
+    out = p.new_output()
+    out.fill_(-1)
+    p.dump_tiles(out, sel, reset=True)
+    torch.cuda.synchronize()
+    i, j = oracle.tri_index(n_in)
+    in_tile = (i >= 64) & (j < 64)
+    got = out.cpu().numpy()
+    np.testing.assert_array_equal(got[:, in_tile], total[:, in_tile])
+    assert (got[:, ~in_tile] == -1).all()
+    total[:, in_tile] = 0
+    out, info = p.accumulate_dump(xs[-1])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), total + refs[-1])
+    p.close()
+
+
 def test_error_paths_enqueue_nothing():
     X = xc()
     x = synth.random_input(2, 64, 64, "ci4", seed=9, device=DEV)
