@@ -76,9 +76,21 @@ typedef enum {
  * that would take a window past fold_bound fails with XCORR_ERR_ARG and
  * changes nothing.  Not with the fp paths. */
 
+/* Input counts: the kernels read rows of a multiple of 4 inputs (4-bit
+ * samples) or 2 (8-bit), and the LDS-DMA tiles rows of a multiple of 16.
+ * A plan whose n_inputs is not such a multiple first copies each chunk of
+ * the caller's input, zero padded to that width, into a staging buffer it
+ * holds and grows to its largest chunk (one extra pass over the input;
+ * zero inputs add nothing, so results are unchanged).  The default tile
+ * pads to 16 from 160 inputs up, where the window is bound by the matrix
+ * cores; below that, rows that are a multiple of 4 (2) are read as they
+ * are by the register tile.  Growing the buffer waits for the plan's
+ * stream and allocates, as the 8-bit plane staging below does; xcorr_plan_bytes
+ * does not count it. */
+
 /* Tile variants of the int8 path (xcorr_plan_desc.tile).  All give identical
  * (exact) results; they differ in how samples reach LDS. */
-/* LDS-DMA tiles need n_inputs % 16 == 0.  With 8-bit samples a single plan
+/* With 8-bit samples a single LDS-DMA plan
  * first splits each chunk's rows into real and imaginary planes (one HBM
  * pass into a staging buffer the plan holds and grows to its largest chunk,
  * which xcorr_plan_bytes does not count).  Growing it waits for the plan's
@@ -99,7 +111,7 @@ typedef enum {
 typedef struct xcorr_plan_s* xcorr_plan_t;
 
 typedef struct {
-    int32_t n_inputs;            /* N_i >= 1, multiple of 4 (CI4) or 2 (CI8)          */
+    int32_t n_inputs;            /* N_i, 1 .. 32768 (any count; see below)            */
     int32_t n_channels;          /* N_c >= 1                                          */
     int32_t format;              /* xcorr_format                                      */
     int32_t path;                /* xcorr_path                                        */

@@ -60,13 +60,76 @@ int64_t row_bytes_of(const xcorr_plan_s* p)
     return (int64_t)p->d.n_inputs * (p->d.format == XCORR_CI4 ? 1 : 2);
 }
 
+int64_t staged_row_bytes(const xcorr_plan_s* p)
+{
+    return (int64_t)p->n_cols * (p->d.format == XCORR_CI4 ? 1 : 2);
+}
+
+// Zero inputs add nothing, so any input count can be padded.  The kernels
+// load rows in dwords (4 inputs of 4-bit samples, 2 of 8-bit ones); the
+// LDS-DMA int8 kernels read 16-input chunks.  Rows of other widths are
+// padded to those multiples by a copy of each chunk (one pass over the
+// input).  For fewer than 160 inputs, where the window is bound by HBM
+// rather than by the matrix cores, the default tile keeps such rows in the
+// register-staged kernel instead of paying that pass for the LDS-DMA one.
+int cols_of(const xcorr_plan_desc* d)
+{
+    const int n = d->n_inputs;
+    const int align = d->format == XCORR_CI4 ? 4 : 2;
+    int c = (n + align - 1) / align * align;
+    const bool dma_tile = d->tile == kTileDma4 || d->tile == kTileDma8;
+    if (d->path == XCORR_PATH_I8_MFMA && n % 16 && (dma_tile || (d->tile == kTileDefault && n >= 160)))
+        c = (n + 15) / 16 * 16;
+    return c;
+}
+
+xcorr_status grow_buffer(xcorr_plan_s* p, hipStream_t stream, void** buf, size_t* bytes, size_t need, const char* what)
+{
+    if (*bytes >= need) return XCORR_OK;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess && stream != p->stream) e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess) {
+        if (*buf) (void)hipFree(*buf);
+        *buf = nullptr;
+        *bytes = 0;
+        e = hipMalloc(buf, need);
+        if (e == hipSuccess) *bytes = need;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(XCORR_ERR_NOMEM, "%s (%zu bytes): %s", what, need, hipGetErrorString(e));
+    }
+    return XCORR_OK;
+}
+
+xcorr_status stage_chunk(xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int64_t t_len, hipStream_t stream,
+                         const uint8_t** out, int64_t* out_stride)
+{
+    if (p->n_cols == p->d.n_inputs) {
+        *out = in;
+        *out_stride = chan_stride;
+        return XCORR_OK;
+    }
+    const int64_t srow = staged_row_bytes(p);
+    xcorr_status s = grow_buffer(p, stream, (void**)&p->d_pad, &p->pad_bytes,
+                                 (size_t)srow * t_len * p->d.n_channels, "row padding");
+    if (s != XCORR_OK) return s;
+    hipError_t e = launch_pad_rows(p->d_pad, (int)srow, in, (int)row_bytes_of(p), chan_stride, nullptr, t_len,
+                                   p->d.n_channels, stream);
+    if (e != hipSuccess) return hip_fail(e, "row padding");
+    *out = p->d_pad;
+    *out_stride = srow * t_len;
+    return XCORR_OK;
+}
+
 LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
                       const void* src, void* dst, int mode)
 {
     LaunchArgs a;
     a.in = in;
     a.chan_stride = chan_stride;
-    a.row_bytes = (int32_t)row_bytes_of(p);
+    a.row_bytes = (int32_t)staged_row_bytes(p);
+    a.n_cols = p->n_cols;
     a.n_inputs = p->d.n_inputs;
     a.t_len = t_len;
     a.n_channels = p->d.n_channels;
@@ -75,7 +138,6 @@ LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_str
     a.n_blocks = p->n_items * p->n_groups;
     a.xcd_map = p->xcd_map;
     a.out32 = mode;
-    a.reserved = 0;
     a.items = p->d_items;
     a.src = src;
     a.dst = dst;
@@ -163,7 +225,7 @@ int64_t fold_bound_of(const xcorr_plan_desc* d)
     const int64_t b = d->path == XCORR_PATH_I8_MFMA ? 65535 : (int64_t)1 << 30;
     // one launch's samples of one channel must stay below 2^31 bytes (the
     // kernels address a channel through a 32-bit buffer range)
-    const int64_t row = (int64_t)d->n_inputs * (d->format == XCORR_CI4 ? 1 : 2);
+    const int64_t row = (int64_t)cols_of(d) * (d->format == XCORR_CI4 ? 1 : 2);
     return std::min<int64_t>(b, ((int64_t)1 << 31) / row - 1);
 }
 
@@ -212,10 +274,6 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
         return fail(XCORR_ERR_ARG, "n_inputs and n_channels must be >= 1");
     if (d->n_inputs > 32768)
         return fail(XCORR_ERR_UNSUPPORTED, "n_inputs %d above 32768", d->n_inputs);
-    const int align = d->format == XCORR_CI4 ? 4 : 2;
-    if (d->n_inputs % align)
-        return fail(XCORR_ERR_UNSUPPORTED, "n_inputs must be a multiple of %d for this format",
-                    align);
     if (d->flags & ~(XCORR_FLAG_NO_XCD_MAP | XCORR_FLAG_NO_PERSIST | XCORR_FLAG_OUT_I32))
         return fail(XCORR_ERR_ARG, "unknown flags 0x%x", d->flags);
     if ((d->flags & XCORR_FLAG_OUT_I32) && d->path != XCORR_PATH_I8_MFMA)
@@ -223,8 +281,6 @@ xcorr_status check_desc(const xcorr_plan_desc* d)
     if (d->tile < 0 || d->tile > kTileRegs) return fail(XCORR_ERR_ARG, "unknown tile variant %d", d->tile);
     if (d->tile != kTileDefault && d->path != XCORR_PATH_I8_MFMA)
         return fail(XCORR_ERR_UNSUPPORTED, "tile variants exist for the int8 path only");
-    if ((d->tile == kTileDma8 || d->tile == kTileDma4) && d->n_inputs % 16)
-        return fail(XCORR_ERR_UNSUPPORTED, "LDS-DMA tiles need n_inputs %% 16 == 0");
     if (d->tile == kTileDma8 && d->format != XCORR_CI4)
         return fail(XCORR_ERR_UNSUPPORTED, "the DMA8 tile takes 4-bit samples");
     return XCORR_OK;
@@ -253,32 +309,22 @@ void release_side(xcorr_plan_t p)
     p->side = nullptr;
 }
 
+// in: rows of n_cols inputs (already staged).
 xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
                           const void* src, void* dst, int mode)
 {
     LaunchArgs a = chunk_args(p, in, chan_stride, t_len, src, dst, mode);
     hipError_t e;
     if (p->d.path == XCORR_PATH_I8_MFMA && p->d.format == XCORR_CI8 && p->tile != kTileRegs &&
-        p->d.n_inputs % 16 == 0) {
+        p->n_cols % 16 == 0) {
         // the LDS-DMA kernel reads the chunk with each row split into its
         // real and imaginary planes: one HBM pass into the plan's staging
         // buffer (grown to the largest chunk seen)
-        const int64_t row = row_bytes_of(p);
+        const int64_t row = staged_row_bytes(p);
         const size_t need = (size_t)row * t_len * p->d.n_channels;
-        if (p->planes_bytes < need) {
-            e = hipStreamSynchronize(p->stream);
-            if (e == hipSuccess) {
-                if (p->d_planes) (void)hipFree(p->d_planes);
-                p->d_planes = nullptr;
-                p->planes_bytes = 0;
-                e = hipMalloc((void**)&p->d_planes, need);
-                if (e == hipSuccess) p->planes_bytes = need;
-            }
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(XCORR_ERR_NOMEM, "8-bit plane staging (%zu bytes): %s", need, hipGetErrorString(e));
-            }
-        }
+        xcorr_status gs = grow_buffer(p, p->stream, (void**)&p->d_planes, &p->planes_bytes, need,
+                                      "8-bit plane staging");
+        if (gs != XCORR_OK) return gs;
         // The split is an HBM pass and the kernel an MFMA-bound one: with
         // enough channels, split the channels into groups and run the split
         // of every group on a side stream, so that the kernel of group g
@@ -297,7 +343,7 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
             }
         }
         if (!overlap) {
-            e = launch_ci8_planes(in, chan_stride, p->d.n_inputs, t_len, n_ch, p->d_planes, p->stream);
+            e = launch_ci8_planes(in, chan_stride, p->n_cols, t_len, n_ch, p->d_planes, p->stream);
             if (e != hipSuccess) return hip_fail(e, "8-bit plane split");
             a = chunk_args(p, p->d_planes, row * t_len, t_len, src, dst, mode);
         } else {
@@ -309,7 +355,7 @@ xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride
             e = hipEventRecord(p->side_ev[kPlaneGroups], p->stream);
             if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->side_ev[kPlaneGroups], 0);
             for (int g = 0; e == hipSuccess && g < kPlaneGroups; ++g) {
-                e = launch_ci8_planes(in + c_at[g] * chan_stride, chan_stride, p->d.n_inputs, t_len,
+                e = launch_ci8_planes(in + c_at[g] * chan_stride, chan_stride, p->n_cols, t_len,
                                       c_at[g + 1] - c_at[g], p->d_planes + c_at[g] * row * t_len, p->side);
                 if (e == hipSuccess) e = hipEventRecord(p->side_ev[g], p->side);
             }
@@ -351,9 +397,9 @@ xcorr_status run_window(xcorr_plan_t p, const void* d_in, int64_t n_time, void* 
 }  // namespace
 
 xcorr_status xcorr::run_window_strided(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride,
-                                       int64_t n_time, void* final_dst)
+                                       int64_t n_time, void* final_dst, bool staged)
 {
-    const int64_t row = row_bytes_of(p);
+    const int64_t row = staged ? staged_row_bytes(p) : row_bytes_of(p);
     AccState st = acc_state(p);
     for (int64_t t0 = 0; t0 < n_time; t0 += p->fold_bound) {
         const int64_t len = std::min<int64_t>(p->fold_bound, n_time - t0);
@@ -363,7 +409,13 @@ xcorr_status xcorr::run_window_strided(xcorr_plan_t p, const uint8_t* in, int64_
             hipError_t e = fold_acc32(p, t.fold_acc_valid, p->stream);
             if (e != hipSuccess) return hip_fail(e, "int32 accumulator fold");
         }
-        xcorr_status s = launch_chunk(p, in + t0 * row, chan_stride, (int32_t)len, t.src, t.dst, t.mode);
+        const uint8_t* cin = in + t0 * row;
+        int64_t cstride = chan_stride;
+        if (!staged) {
+            xcorr_status s = stage_chunk(p, cin, chan_stride, len, p->stream, &cin, &cstride);
+            if (s != XCORR_OK) return s;
+        }
+        xcorr_status s = launch_chunk(p, cin, cstride, (int32_t)len, t.src, t.dst, t.mode);
         if (s != XCORR_OK) return s;
         set_acc_state(p, st);
     }
@@ -429,6 +481,7 @@ xcorr_status xcorr_plan(xcorr_plan_t* out, const xcorr_plan_desc* d)
     const int n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     p->persist_grid = (d->flags & XCORR_FLAG_NO_PERSIST) ? 0 : (n_cu + 7) / 8 * 8;
     p->fold_bound = fold_bound_of(d);
+    p->n_cols = cols_of(d);
     // the int32 accumulator holds true sums (not the kernel's scaled
     // partials): at most 2 * 8 * 8 = 128 per sample for 4-bit samples and
     // 2 * 128 * 128 for 8-bit samples in magnitude
@@ -710,6 +763,7 @@ xcorr_status xcorr_destroy(xcorr_plan_t p)
     release(p->d_counters);
     release(p->d_tile_sel);
     release(p->d_planes);
+    release(p->d_pad);
     release(p->d_gate_buf);
     release(p->d_gate_idx);
     release_side(p);

@@ -65,6 +65,31 @@ __global__ void __launch_bounds__(256) add_i32_kernel(longlong2* out, const long
     }
 }
 
+// Row c, t of out (out_row bytes) = row c, src(t) of in (in_row <= out_row
+// bytes, src(t) = idx[t] or t) followed by zeros.  One thread per output
+// dword; the input is read bytewise (its rows need no alignment).
+__global__ void __launch_bounds__(256) pad_rows_kernel(uint8_t* out, int out_row, const uint8_t* in, int in_row,
+                                                       int64_t in_chan_stride, const int32_t* idx, int64_t n_rows,
+                                                       int n_channels)
+{
+    const int per_row = out_row / 4;
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_rows * per_row) return;
+    const int64_t t = u / per_row;
+    const int q = (int)(u - t * per_row);
+    const int64_t ts = idx ? idx[t] : t;
+    for (int c = blockIdx.y; c < n_channels; c += gridDim.y) {
+        const uint8_t* src = in + c * in_chan_stride + ts * in_row;
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int k = 4 * q + b;
+            if (k < in_row) v |= (uint32_t)src[k] << (8 * b);
+        }
+        *(uint32_t*)(out + ((int64_t)c * n_rows + t) * out_row + 4 * q) = v;
+    }
+}
+
 int grid_for(size_t n)
 {
     const size_t b = (n + 255) / 256;
@@ -94,6 +119,19 @@ hipError_t launch_add_i32(void* out, const void* a64, const void* a32, size_t n_
 {
     hipLaunchKernelGGL(add_i32_kernel, dim3(grid_for(n_pairs)), dim3(256), 0, s, (longlong2*)out,
                        (const longlong2*)a64, (const int2*)a32, n_pairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_rows(uint8_t* out, int out_row, const uint8_t* in, int in_row, int64_t in_chan_stride,
+                           const int32_t* idx, int64_t n_rows, int n_channels, hipStream_t s)
+{
+    if (n_rows <= 0 || n_channels <= 0) return hipSuccess;
+    if (out_row % 4 || in_row > out_row) return hipErrorInvalidValue;
+    const int64_t gx = (n_rows * (out_row / 4) + 255) / 256;
+    if (gx > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)gx, n_channels < 65535 ? n_channels : 65535);
+    hipLaunchKernelGGL(pad_rows_kernel, grid, dim3(256), 0, s, out, out_row, in, in_row, in_chan_stride, idx, n_rows,
+                       n_channels);
     return hipGetLastError();
 }
 

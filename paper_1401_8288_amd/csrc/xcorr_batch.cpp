@@ -174,9 +174,12 @@ xcorr_status run_step(xcorr_batch_t b, const void* const* d_in, const int64_t* n
                 hipError_t e = fold_acc32(p, t.fold_acc_valid, b->stream);
                 if (e != hipSuccess) return hip_fail(e, "int32 accumulator fold");
             }
+            const uint8_t* cin = (const uint8_t*)d_in[k] + t0 * row;
+            int64_t cstride = row * n_time[k];
+            xcorr_status ss = stage_chunk(p, cin, cstride, len, b->stream, &cin, &cstride);
+            if (ss != XCORR_OK) return ss;
             Entry en;
-            en.a = chunk_args(p, (const uint8_t*)d_in[k] + t0 * row, row * n_time[k], (int32_t)len, t.src, t.dst,
-                              t.mode);
+            en.a = chunk_args(p, cin, cstride, (int32_t)len, t.src, t.dst, t.mode);
             en.t_len = len;
             en.plan = p;
             es.push_back(en);
@@ -234,7 +237,7 @@ xcorr_status check_config(xcorr_batch_t b, const xcorr_batch_config& c)
 {
     if (c.tile < 0 || c.tile > kTileRegs) return fail(XCORR_ERR_ARG, "unknown tile %d", c.tile);
     if ((c.tile == kTileDma8 || c.tile == kTileDma4) && !b->dma_ok)
-        return fail(XCORR_ERR_UNSUPPORTED, "LDS-DMA tiles need 4-bit samples and n_inputs %% 16 == 0");
+        return fail(XCORR_ERR_UNSUPPORTED, "LDS-DMA tiles need 4-bit samples in rows of 16 inputs");
     if (c.grid < 8 || c.grid % 8 || c.grid > 65536) return fail(XCORR_ERR_ARG, "grid must be a multiple of 8");
     if (c.balance != 0 && c.balance != 1) return fail(XCORR_ERR_ARG, "balance must be 0 or 1");
     return XCORR_OK;
@@ -275,7 +278,7 @@ xcorr_status xcorr_batch_create(xcorr_batch_t* out, const xcorr_plan_t* plans, i
         if (p->d.path != XCORR_PATH_I8_MFMA) return fail(XCORR_ERR_UNSUPPORTED, "batches use the int8 path");
         if (fmt >= 0 && p->d.format != fmt) return fail(XCORR_ERR_ARG, "plans of a batch must share the format");
         fmt = p->d.format;
-        dma_ok = dma_ok && p->d.format == XCORR_CI4 && p->d.n_inputs % 16 == 0;
+        dma_ok = dma_ok && p->d.format == XCORR_CI4 && p->n_cols % 16 == 0;
         for (int j = 0; j < k; ++j)
             if (plans[j] == plans[k]) return fail(XCORR_ERR_ARG, "plan %d appears twice", k);
     }
@@ -534,37 +537,22 @@ xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, 
         for (int64_t t = 0; t < n_time; ++t)
             if (gate[t] != 0xFF) idx[pos[gate[t]]++] = (int32_t)t;
     }
-    const int64_t row = row_bytes_of(p0);
-    const size_t need = (size_t)kept * row * p0->d.n_channels;
-    hipError_t e = hipSuccess;
-    if (p0->gate_buf_bytes < need) {
-        e = hipStreamSynchronize(p0->stream);
-        if (e == hipSuccess) {
-            if (p0->d_gate_buf) (void)hipFree(p0->d_gate_buf);
-            p0->d_gate_buf = nullptr;
-            p0->gate_buf_bytes = 0;
-            e = hipMalloc(&p0->d_gate_buf, need);
-            if (e == hipSuccess) p0->gate_buf_bytes = need;
-        }
-    }
-    if (e == hipSuccess && p0->gate_idx_bytes < (size_t)kept * 4) {
-        e = hipStreamSynchronize(p0->stream);
-        if (e == hipSuccess) {
-            if (p0->d_gate_idx) (void)hipFree(p0->d_gate_idx);
-            p0->d_gate_idx = nullptr;
-            p0->gate_idx_bytes = 0;
-            e = hipMalloc((void**)&p0->d_gate_idx, (size_t)kept * 4);
-            if (e == hipSuccess) p0->gate_idx_bytes = (size_t)kept * 4;
-        }
-    }
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(XCORR_ERR_NOMEM, "gating buffers: %s", hipGetErrorString(e));
-    }
-    e = hipMemcpyAsync(p0->d_gate_idx, idx.data(), (size_t)kept * 4, hipMemcpyHostToDevice, p0->stream);
+    // rows of the packed buffer: the kernels' row width (zero padded when
+    // the plans' rows need it), so the gates' launches read it as it is
+    const int64_t row = row_bytes_of(p0), prow = staged_row_bytes(p0);
+    xcorr_status gs = grow_buffer(p0, p0->stream, &p0->d_gate_buf, &p0->gate_buf_bytes,
+                                  (size_t)kept * prow * p0->d.n_channels, "gated samples");
+    if (gs == XCORR_OK)
+        gs = grow_buffer(p0, p0->stream, (void**)&p0->d_gate_idx, &p0->gate_idx_bytes, (size_t)kept * 4,
+                         "gated sample indices");
+    if (gs != XCORR_OK) return gs;
+    hipError_t e = hipMemcpyAsync(p0->d_gate_idx, idx.data(), (size_t)kept * 4, hipMemcpyHostToDevice, p0->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p0->stream);   // idx is a host temporary
     if (e == hipSuccess)
-        e = launch_gather_rows(p0->d_gate_buf, d_in, p0->d_gate_idx, kept, n_time, row, p0->d.n_channels, p0->stream);
+        e = prow == row ? launch_gather_rows(p0->d_gate_buf, d_in, p0->d_gate_idx, kept, n_time, row,
+                                             p0->d.n_channels, p0->stream)
+                        : launch_pad_rows((uint8_t*)p0->d_gate_buf, (int)prow, (const uint8_t*)d_in, (int)row,
+                                          row * n_time, p0->d_gate_idx, kept, p0->d.n_channels, p0->stream);
     if (e != hipSuccess) return hip_fail(e, "gate gather");
 
     // One launch (per fold chunk) per gate, each over all channels: a gate
@@ -573,7 +561,7 @@ xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, 
     const uint8_t* packed = (const uint8_t*)p0->d_gate_buf;
     for (int g = 0; g < n_gates; ++g) {
         if (cnt[g] == 0) continue;
-        st = run_window_strided(plans[g], packed + off[g] * row, row * kept, cnt[g], nullptr);
+        st = run_window_strided(plans[g], packed + off[g] * prow, prow * kept, cnt[g], nullptr, true);
         if (st != XCORR_OK) return st;
     }
     for (int g = 0; g < n_gates; ++g) {

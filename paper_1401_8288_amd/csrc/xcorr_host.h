@@ -33,6 +33,12 @@ struct xcorr_plan_s {
     int n_items = 0;                // items per channel group
     int ch_group = 1;
     int n_groups = 0;
+    // Inputs per row of what the kernels read: n_inputs, or more when the
+    // caller's rows must be staged zero padded (alignment of the kernels'
+    // loads, or the 16-input rows of the LDS-DMA kernels).
+    int n_cols = 0;
+    uint8_t* d_pad = nullptr;       // padded copy of a chunk (grows on use)
+    size_t pad_bytes = 0;
     int xcd_map = 1;
     int out32 = 0;                  // int32 (re, im) output (XCORR_FLAG_OUT_I32)
     int tile = 0;                   // int8 tile variant in use
@@ -61,6 +67,16 @@ xcorr_status hip_fail(hipError_t e, const char* what);
 bool plan_live(xcorr_plan_t p);
 xcorr_status check_ptr(const void* ptr, const char* name);
 int64_t row_bytes_of(const xcorr_plan_s* p);
+// Bytes per row of what the kernels read (n_cols inputs).
+int64_t staged_row_bytes(const xcorr_plan_s* p);
+// The buffer a chunk's launch reads: in itself, or (n_cols > n_inputs) a
+// zero-padded copy in the plan's pad buffer, enqueued on stream.  in: the
+// caller's layout (rows of n_inputs, channel c at in + c * chan_stride).
+xcorr_status stage_chunk(xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int64_t t_len, hipStream_t stream,
+                         const uint8_t** out, int64_t* out_stride);
+// Grows one of a plan's staging buffers to at least `need` bytes (waits for
+// stream and the plan's stream first: the old buffer may be in use).
+xcorr_status grow_buffer(xcorr_plan_s* p, hipStream_t stream, void** buf, size_t* bytes, size_t need, const char* what);
 // Launch arguments of one time chunk of a plan.
 LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
                       const void* src, void* dst, int mode);
@@ -99,8 +115,11 @@ int64_t fold_bound_of(const xcorr_plan_desc* d);
 // (channel c's rows start at in + c * chan_stride), split at the fold bound.
 // If final_dst is non-null the last launch writes its result there instead
 // of into the accumulator.
+// staged: in already has rows of n_cols inputs (no padding pass).
 xcorr_status run_window_strided(xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int64_t n_time,
-                                void* final_dst);
+                                void* final_dst, bool staged = false);
+// Inputs per row the kernels of a plan with this descriptor read.
+int cols_of(const xcorr_plan_desc* d);
 // Relative cost of a work item (MFMA blocks its waves own).
 int item_blocks(const WorkItem& it);
 // Work items of a plan (xcorr_items.cpp) for W row blocks of 64 inputs:

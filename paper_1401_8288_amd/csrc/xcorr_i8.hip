@@ -234,7 +234,7 @@ struct DmaStager2 : DmaStager {
             const int q = (lane & 3) ^ swz(row);
             const int input = (w.stage_rb < 0 ? 0 : w.stage_rb) * kRowBlock + 16 * q;
             vofs_im[j] = (uint32_t)row * (uint32_t)a.row_bytes +
-                         (input < a.n_inputs ? (uint32_t)(a.n_inputs + input) : 0x80000000u);
+                         (input < a.n_inputs ? (uint32_t)(a.n_cols + input) : 0x80000000u);
         }
     }
 
@@ -1046,10 +1046,11 @@ hipError_t launch_persist_single(const LaunchArgs& a, int grid, int* counters, h
     return launch_batch_variant<FMT>(ba, g, s);
 }
 
-int variant_of(int fmt, int n_inputs, int tile)
+// n_cols: inputs per row of the buffer the kernel reads.
+int variant_of(int fmt, int n_cols, int tile)
 {
-    if (fmt == 1) return (tile == kTileRegs || n_inputs % 16 != 0) ? V_CI8 : V_CI8_DMA4;
-    if (tile == kTileRegs || n_inputs % 16 != 0) return V_CI4;
+    if (fmt == 1) return (tile == kTileRegs || n_cols % 16 != 0) ? V_CI8 : V_CI8_DMA4;
+    if (tile == kTileRegs || n_cols % 16 != 0) return V_CI4;
     return tile == kTileDma8 ? V_CI4_DMA8 : V_CI4_DMA4;
 }
 
@@ -1057,7 +1058,7 @@ int variant_of(int fmt, int n_inputs, int tile)
 
 hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, int* counters, hipStream_t s)
 {
-    switch (variant_of(fmt, a.n_inputs, tile)) {
+    switch (variant_of(fmt, a.n_cols, tile)) {
     case V_CI8:      return launch_variant<V_CI8>(a, s);
     case V_CI4:      return launch_variant<V_CI4>(a, s);
     case V_CI8_DMA4: return persist_grid ? launch_persist_single<V_CI8_DMA4>(a, persist_grid, counters, s)
@@ -1074,7 +1075,7 @@ hipError_t launch_i8_batch(const BatchArgs& ba, int fmt, int tile, int grid, hip
     // one variant for the whole launch: the DMA variants need every entry's
     // n_inputs to be a multiple of 16
     int n16 = 1;
-    for (int e = 0; e < ba.n_entries; ++e) n16 &= ba.e[e].n_inputs % 16 == 0;
+    for (int e = 0; e < ba.n_entries; ++e) n16 &= ba.e[e].n_cols % 16 == 0;
     // 8-bit batches stay on the register-staged kernel: the two-plane
     // layout of V_CI8_DMA4 is made by the single-plan launch path only
     const int v = fmt == 1 ? V_CI8 : variant_of(fmt, n16 ? 16 : 4, tile);

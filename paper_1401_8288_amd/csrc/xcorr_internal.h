@@ -69,7 +69,7 @@ struct LaunchArgs {
     int32_t xcd_map;               // 1: XCD-aware block -> item mapping
     int32_t out32;                 // result mode: 0 int64 (re, im) pairs (src int64); 1 int32 pairs
                                    // (src int32); 2 int64 pairs added to an int32 src
-    int32_t reserved;
+    int32_t n_cols;                // inputs per row of the buffer read (>= n_inputs; the rest zero)
     const WorkItem* items;
     const void* src;               // optional accumulator to add (same layout as dst)
     void* dst;                     // result: [channel][tri][2]
@@ -170,6 +170,11 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // out = a64 + a32 over n_pairs (re, im) pairs: out and a64 int64, a32 int32;
 // either source may be null (zero); out may equal a64.
 hipError_t launch_add_i32(void* out, const void* a64, const void* a32, size_t n_pairs, hipStream_t s);
+// out[c][t] (rows of out_row bytes, out_row % 4 == 0) = in row (c, idx ? idx[t]
+// : t) of in_row bytes (channel c at in + c * in_chan_stride), zero padded;
+// t < n_rows, out channels n_rows rows apart.
+hipError_t launch_pad_rows(uint8_t* out, int out_row, const uint8_t* in, int in_row, int64_t in_chan_stride,
+                           const int32_t* idx, int64_t n_rows, int n_channels, hipStream_t s);
 // 8-bit samples [channel][time][input][re, im] (channel c at in + c *
 // chan_stride) -> out[channel][time][re of every input, then im of every
 // input] (rows of the same 2 n_inputs bytes); n_inputs % 8 == 0.

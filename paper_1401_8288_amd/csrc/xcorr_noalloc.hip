@@ -138,7 +138,7 @@ extern "C" xcorr_status xcorr_correlate_noalloc(const xcorr_plan_desc* d, const 
     a.n_blocks = (int32_t)(t.items.size() * n_groups);
     a.xcd_map = (d->flags & XCORR_FLAG_NO_XCD_MAP) ? 0 : 1;
     a.out32 = (d->flags & XCORR_FLAG_OUT_I32) ? 1 : 0;
-    a.reserved = 0;
+    a.n_cols = d->n_inputs;
     a.items = items;
     a.src = nullptr;
     a.dst = d_out;

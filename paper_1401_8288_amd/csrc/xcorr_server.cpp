@@ -154,7 +154,7 @@ xcorr_status launch_windows(xcorr_server_t s, const std::vector<xcorr_plan_t>& p
     std::map<int, std::vector<size_t>> groups;
     for (size_t k = 0; k < plans.size(); ++k) {
         const xcorr_plan_s* p = plans[k];
-        const int key = p->d.format == XCORR_CI8 ? 2 : (p->d.n_inputs % 16 == 0 ? 0 : 1);
+        const int key = p->d.format == XCORR_CI8 ? 2 : (p->n_cols % 16 == 0 ? 0 : 1);
         groups[key].push_back(k);
     }
     L.info.assign(plans.size(), xcorr_dump_info{});

@@ -40,7 +40,8 @@ def pulsar_gates(n_t, period, phase=0):
     return g
 
 
-@pytest.mark.parametrize("n_in,fmt", [(96, "ci4"), (36, "ci4"), (64, "ci8")])
+@pytest.mark.parametrize("n_in,fmt", [(96, "ci4"), (36, "ci4"), (64, "ci8"), (6, "ci4"), (171, "ci4"),
+                                      (7, "ci8")])
 def test_gated_accumulation_matches_oracle(n_in, fmt):
     say("gating", n_in, fmt)
     X = xc()

@@ -170,9 +170,11 @@ def test_graph_replays_match_eager():
 
 
 def test_batch_register_staged_and_ci8():
-    say("batch: n_inputs not a multiple of 16 (register staging) and 8-bit samples")
-    subs = [(36, 3, 300), (100, 2, 129), (16, 5, 64)]
-    for fmt in ("ci4", "ci8"):
+    say("batch: n_inputs not a multiple of 16 (register staging), rows zero padded, and 8-bit samples")
+    for subs, fmt in (([(36, 3, 300), (100, 2, 129), (16, 5, 64)], "ci4"),
+                      ([(36, 3, 300), (100, 2, 129), (16, 5, 64)], "ci8"),
+                      ([(6, 3, 300), (66, 2, 129), (514, 1, 64)], "ci4"),
+                      ([(5, 3, 300), (33, 2, 129)], "ci8")):
         xs = inputs(subs, fmt=fmt, seed=51)
         refs = oracle_of(xs, fmt)
         plans, b = make(subs, fmt)

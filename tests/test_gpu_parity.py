@@ -66,7 +66,10 @@ def test_tiny_workload_all_paths(path):
 
 SHAPES = [  # (n_in, n_ch, n_t): ragged inputs, ragged time, channel groups
     (4, 3, 1), (4, 5, 64), (8, 6, 65), (36, 5, 100), (64, 9, 129), (100, 2, 129),
-    (128, 3, 64), (192, 2, 65), (256, 2, 200), (400, 2, 77), (516, 1, 70)]
+    (128, 3, 64), (192, 2, 65), (256, 2, 200), (400, 2, 77), (516, 1, 70),
+    # input counts that are not a multiple of 4 (rows zero padded for the
+    # kernels' loads; 160 and more to 16 for the LDS-DMA kernels)
+    (1, 2, 5), (2, 3, 7), (3, 2, 64), (6, 4, 100), (66, 3, 130), (130, 2, 65), (161, 2, 70), (514, 1, 70)]
 
 
 @pytest.mark.parametrize("fmt", ["ci4", "ci8"])
@@ -194,6 +197,33 @@ def test_int8_tile_variants(tile, shape):
     ref = oracle.correlate(x.cpu().numpy(), "ci4")
     got, _ = run(x, "ci4", "i8", tile=tile)
     np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("shape", [(6, 3, 100), (36, 2, 129), (99, 2, 70), (514, 1, 65)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_dma_tiles_on_padded_rows(tile, shape):
+    # an LDS-DMA tile asked for rows that are not a multiple of 16 inputs:
+    # each chunk is staged zero padded; int64 and int32 output, and a window
+    # split over calls (the second call adds)
+    n_in, n_ch, n_t = shape
+    say("dma tile on padded rows", tile, shape)
+    x = synth.random_input(n_ch, n_t, n_in, "ci4", seed=tile * 7 + n_in, device=DEV)
+    ref = oracle.correlate(x.cpu().numpy(), "ci4")
+    got, _ = run(x, "ci4", "i8", tile=tile)
+    np.testing.assert_array_equal(got, ref)
+    got32, _ = run(x, "ci4", "i8", tile=tile, flags=xc().FLAG_OUT_I32)
+    np.testing.assert_array_equal(got32.astype(np.int64), ref)
+    p = xc().Plan(n_in, n_ch, "ci4", "i8", tile=tile)
+    p.accumulate(x[:, : n_t // 2].contiguous())
+    out, _ = p.accumulate_dump(x[:, n_t // 2:].contiguous())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+    p.close()
+    if tile == 2:
+        x8 = synth.random_input(n_ch, n_t, n_in, "ci8", seed=tile * 5 + n_in, lo=-128, hi=127, device=DEV)
+        got, _ = run(x8, "ci8", "i8", tile=tile)
+        np.testing.assert_array_equal(got, oracle.correlate(x8.cpu().numpy(), "ci8"))
 
 
 @pytest.mark.parametrize("tile", [2, 3])
