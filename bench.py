@@ -195,28 +195,22 @@ def copy_calibration(torch, xcorr, x, w):
     p.close()
 
 
-def serving_leg(torch, xcorr, seconds, speedup, seed=7):
-    """Batched streaming: the five subarrays (32/96/192/400/704 inputs, 4-bit)
-    feed windows of 1024-4096 samples into the server as Poisson processes
-    whose mean gap is the window's duration (N_t x 40.96 us) divided by
-    `speedup`.  The deadline of a window is that same duration / speedup."""
+def run_serving(torch, xcorr, pool, shapes, seconds, speedup, seed, tune_path=None, inflight=1):
+    """Streams of the given shapes feed windows of 1024-4096 samples into the
+    server as Poisson processes whose mean gap is the window's duration
+    (N_t x 40.96 us) divided by `speedup`; a window's deadline is that same
+    duration / speedup after its arrival."""
     import random
     from paper_1401_8288_amd import synth
     rng = random.Random(seed)
-    dev = torch.device("cuda:0")
     lens = (1024, 2048, 3072, 4096)
-    pool, outs, busy = [], [], []
-    for k in range(len(synth.SUBARRAYS)):
-        pool.append({t: synth.generate(synth.subarray_workload(k, t), device=dev) for t in lens})
-    torch.cuda.synchronize()
-    srv = xcorr.Server(device_budget=64 << 30, max_streams=8, max_inflight=2)
-    sids = []
-    for k in range(len(synth.SUBARRAYS)):
-        w = synth.subarray_workload(k, 1024)
-        sids.append(srv.open(w.n_inputs, w.n_channels))
-        outs.append([srv.new_output(sids[-1]) for _ in range(4)])
-        busy.append([None] * 4)
-    # arrival schedule
+    srv = xcorr.Server(device_budget=64 << 30, max_streams=64, max_inflight=inflight, tune_path=tune_path)
+    sids, outs, busy = [], [], []
+    for (n_in, n_ch) in shapes:
+        sids.append(srv.open(n_in, n_ch))
+        srv.set_deadline(sids[-1], synth.SPECTRUM_INTERVAL_S / speedup)
+        outs.append([srv.new_output(sids[-1]) for _ in range(8)])
+        busy.append([None] * 8)
     events = []
     for k in range(len(sids)):
         t = 0.0
@@ -234,28 +228,107 @@ def serving_leg(torch, xcorr, seconds, speedup, seed=7):
         delay = ta - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        slot = next((j for j in range(4) if busy[k][j] is None or srv.poll(busy[k][j])[0]), None)
+        slot = next((j for j in range(8) if busy[k][j] is None or srv.poll(busy[k][j])[0]), None)
         if slot is None:
             srv.wait(busy[k][0])
             slot = 0
         tk = srv.submit(sids[k], pool[k][nt], outs[k][slot])
         busy[k][slot] = tk
         tickets.append((tk, dur))
-    misses = 0
     for tk, dur in tickets:
-        _, lat = srv.wait(tk)
-        misses += lat > dur * 1e3
+        srv.wait(tk)
     st = srv.stats()
+    misses = st["deadline_misses"]
     srv.close()
-    cmac_rt = sum(synth.subarray_workload(k, 1).cmac for k in range(len(sids))) / synth.SPECTRUM_INTERVAL_S
-    return {"workload": "5 subarrays of 16/48/96/200/352 dual-pol antennas, 512/1024/2048/256/128 channels, "
-                        "4+4-bit, Poisson windows of 1024-4096 samples",
-            "speedup_vs_real_time": speedup, "seconds": seconds, "windows": st["windows_done"],
+    cmac_rt = sum(n * (n + 1) // 2 * c for (n, c) in shapes) / synth.SPECTRUM_INTERVAL_S
+    return {"speedup_vs_real_time": speedup, "seconds": seconds, "windows": st["windows_done"],
             "offered_tcmac_s": round(cmac_rt * speedup / 1e12, 3),
             "achieved_tcmac_s": round(st["cmac"] / st["elapsed_s"] / 1e12, 3) if st["elapsed_s"] else None,
             "latency_p50_ms": round(st["latency_p50_ms"], 3), "latency_p99_ms": round(st["latency_p99_ms"], 3),
             "latency_max_ms": round(st["latency_max_ms"], 3), "deadline_misses": int(misses),
-            "launches": st["launches"], "mean_windows_per_launch": round(st["mean_batch"], 2)}
+            "launches": st["launches"], "mean_windows_per_launch": round(st["mean_batch"], 2),
+            "mixes_tuned": st["mixes_tuned"], "max_inflight": inflight}
+
+
+def serving_leg(torch, xcorr, seconds, speedups, seed=7, inflight=1):
+    """Batched streaming of the five subarrays (16/48/96/200/352 dual-pol
+    antennas, 512/1024/2048/256/128 channels, 4-bit), one run per arrival
+    rate (multiple S of real time), with the launch configuration tuned on
+    the first run and kept in a cache file for the later ones.  Reports each
+    run and the largest S without a missed deadline."""
+    import os
+    import tempfile
+    from paper_1401_8288_amd import synth
+    dev = torch.device("cuda:0")
+    lens = (1024, 2048, 3072, 4096)
+    pool = [{t: synth.generate(synth.subarray_workload(k, t), device=dev) for t in lens}
+            for k in range(len(synth.SUBARRAYS))]
+    torch.cuda.synchronize()
+    shapes = [(synth.subarray_workload(k, 1).n_inputs, synth.subarray_workload(k, 1).n_channels)
+              for k in range(len(synth.SUBARRAYS))]
+    tune = os.path.join(tempfile.mkdtemp(prefix="xcorr_tune_"), "tune.txt")
+    runs = [run_serving(torch, xcorr, pool, shapes, seconds, sp, seed, tune, inflight) for sp in speedups]
+    clean = [r["speedup_vs_real_time"] for r in runs if r["deadline_misses"] == 0]
+    return {"workload": "5 subarrays of 16/48/96/200/352 dual-pol antennas, 512/1024/2048/256/128 channels, "
+                        "4+4-bit, Poisson windows of 1024-4096 samples",
+            "runs": runs, "largest_clean_speedup": max(clean) if clean else None}
+
+
+def many_small_leg(torch, xcorr, seconds, speedups, n_sub=32, n_ant=16, n_ch=512, seed=9, inflight=1):
+    """Many small arrays: n_sub subarrays of n_ant dual-pol antennas and n_ch
+    channels, 4-bit.  One step of all of them (4096 samples each) as one
+    batched launch against the same windows as one launch per plan, and the
+    server at each of `speedups` times real time."""
+    from paper_1401_8288_amd import synth
+    dev = torch.device("cuda:0")
+    n_in = 2 * n_ant
+    lens = (1024, 2048, 3072, 4096)
+    pool = []
+    for k in range(n_sub):
+        w = synth.Workload("small%d" % k, n_in, n_ch, 4096, "ci4", "tone", 500 + k,
+                           {"noise_sigma": 2.5, "tone_gain": 0.0})
+        pool.append({t: synth.generate(synth.scaled(w, n_time=t), device=dev) for t in lens})
+    torch.cuda.synchronize()
+    xs = [pool[k][4096] for k in range(n_sub)]
+    plans = [xcorr.Plan(n_in, n_ch, "ci4", "i8") for _ in range(n_sub)]
+    outs = [p.new_output() for p in plans]
+    b = xcorr.Batch(plans)
+    reps = 20
+    for _ in range(3):
+        b.run(xs, outs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    for _ in range(reps):
+        b.run(xs, outs)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / reps
+    stream = plans[0].stream
+    for _ in range(3):
+        for p, x, o in zip(plans, xs, outs):
+            p.accumulate_dump(x, o)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        for p, x, o in zip(plans, xs, outs):
+            p.accumulate_dump(x, o)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1) / reps
+    b.close()
+    for p in plans:
+        p.close()
+    cmac = n_sub * n_in * (n_in + 1) // 2 * n_ch * 4096
+    runs = [run_serving(torch, xcorr, pool, [(n_in, n_ch)] * n_sub, seconds, sp, seed, inflight=inflight)
+            for sp in speedups]
+    clean = [r["speedup_vs_real_time"] for r in runs if r["deadline_misses"] == 0]
+    return {"workload": "%d subarrays of %d dual-pol antennas, %d channels, 4+4-bit" % (n_sub, n_ant, n_ch),
+            "step_4096_samples": {"one_batched_launch_ms": round(ms_batch, 4),
+                                  "one_launch_per_plan_ms": round(ms_seq, 4),
+                                  "batched_speedup": round(ms_seq / ms_batch, 2),
+                                  "tcmac_s_batched": round(cmac / ms_batch / 1e9, 2)},
+            "serving": runs, "largest_clean_speedup": max(clean) if clean else None}
 
 
 def corner_turn_leg(torch, xcorr, w, reps=5, n_fengines=16, spectra_per_packet=8):
@@ -383,6 +456,44 @@ def variants_leg(torch, xcorr, x, w, reps=3, period=700, on=0.09):
                           "gbs": round(3 * frac * w.output_bytes / ms_tiles / 1e6, 1)}}
 
 
+def configs_leg(torch, xcorr, steps=10, warmup=3):
+    """The other array sizes of the workload list, one window each as the
+    headline times it (int8 path, int32 output, fused accumulate + dump):
+    PAPER-like (128 inputs, 1024 channels, 2048 samples, 4-bit: bound by
+    HBM, so its fraction of the 8 TB/s roof is the figure of merit) and
+    large-N (2048 inputs, 256 channels, 8192 samples, 8-bit: bound by the
+    matrix cores).  Also the plain fp32 kernel on the PAPER-like window."""
+    from paper_1401_8288_amd import synth
+    dev = torch.device("cuda:0")
+    res = {}
+    for name in ("paper", "large_n"):
+        w = synth.WORKLOADS[name]
+        x = synth.generate(w, device=dev)
+        torch.cuda.synchronize()
+        ms, out, info = time_path(torch, xcorr, x, w, "i8", steps, warmup, flags=xcorr.FLAG_OUT_I32)
+        del out
+        ops = 8 * w.cmac
+        nbytes = w.input_bytes + w.output_bytes // 2
+        r = {"workload": "%s: %d inputs, %d channels, %d samples/integration, %s"
+                         % (name, w.n_inputs, w.n_channels, w.n_time, w.fmt),
+             "ms_per_step": round(ms, 4), "tcmac_s": round(w.cmac / ms / 1e9, 2),
+             "pct_int8_peak": round(100 * ops / ms / 1e9 / PEAK_INT8_TOPS, 2),
+             "algorithmic_bytes": nbytes, "hbm_gbs": round(nbytes / ms / 1e6, 1),
+             "pct_hbm_peak": round(100 * nbytes / ms / 1e6 / PEAK_HBM_GBS, 2),
+             "bound": "hbm" if name == "paper" else "mfma", "work_items": info.work_items}
+        if name == "paper":
+            fms, fout, _ = time_path(torch, xcorr, x, w, "f32", 3, 1)
+            del fout
+            r["f32_ms_per_step"] = round(fms, 4)
+            r["speedup_int8_vs_fp32"] = round(fms / ms, 2)
+        log("%s: %.4f ms/window, %.1f TCMAC/s, %.1f%% of int8 peak, %.1f%% of HBM peak"
+            % (name, ms, r["tcmac_s"], r["pct_int8_peak"], r["pct_hbm_peak"]))
+        res[name] = r
+        del x
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -425,14 +536,16 @@ def main():
     ap.add_argument("--no-corner-turn", action="store_true", help="skip the corner-turn leg")
     ap.add_argument("--no-fstage", action="store_true", help="skip the F-stage leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the gating / tile-dump leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the PAPER-like and large-N windows")
     ap.add_argument("--workload", default="lwa",
                     help="synthetic workload of the timed window (default lwa, the headline; others for profiling)")
     ap.add_argument("--tile", type=int, default=0,
                     help="int8 tile variant of the timed plans (XCORR_TILE_*; 0 = the library's default)")
-    ap.add_argument("--serving-seconds", type=float, default=4.0,
+    ap.add_argument("--serving-seconds", type=float, default=2.0,
                     help="length of the batched-streaming leg (0 skips it)")
-    ap.add_argument("--serving-speedup", type=float, default=40.0,
-                    help="arrival rate of the streaming leg as a multiple of real time")
+    ap.add_argument("--serving-inflight", type=int, default=1, help="launches the server queues at once")
+    ap.add_argument("--serving-speedups", default="10,20,30,40,60,80,120",
+                    help="arrival rates of the streaming leg, multiples of real time (comma separated)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run the library copy kernel once (for counter calibration)")
     ap.add_argument("--pmc-summary", metavar="DIR",
@@ -560,6 +673,10 @@ def main():
         exact = None
         torch.cuda.empty_cache()
 
+    if not args.no_configs and w.name == "lwa":
+        log("PAPER-like and large-N windows")
+        result["configs"] = configs_leg(torch, xcorr)
+
     if not args.no_corner_turn and w.name == "lwa":
         log("corner turn at the same size")
         result["corner_turn"] = corner_turn_leg(torch, xcorr, w)
@@ -576,9 +693,15 @@ def main():
         log("F-stage:", result["fstage"])
 
     if args.serving_seconds > 0:
-        log("batched streaming leg: %.1f s at %.0fx real time" % (args.serving_seconds, args.serving_speedup))
-        result["serving"] = serving_leg(torch, xcorr, args.serving_seconds, args.serving_speedup)
+        sp = [float(v) for v in args.serving_speedups.split(",") if v]
+        log("batched streaming leg: %.1f s at each of %s x real time" % (args.serving_seconds, sp))
+        result["serving"] = serving_leg(torch, xcorr, args.serving_seconds, sp, inflight=args.serving_inflight)
         log("serving:", result["serving"])
+        torch.cuda.empty_cache()
+        log("many small arrays")
+        result["many_small_arrays"] = many_small_leg(torch, xcorr, args.serving_seconds, [40.0, 200.0, 400.0, 800.0],
+                                                     inflight=args.serving_inflight)
+        log("many small arrays:", result["many_small_arrays"])
         torch.cuda.empty_cache()
 
     if not args.no_cpu:

@@ -378,11 +378,22 @@ xcorr_status xcorr_batch_destroy(xcorr_batch_t batch);
  *     plan of its descriptor (xcorr_plan_bytes); it is admitted when a slot
  *     and that much of the budget are free, else it waits (FIFO) and is
  *     admitted when closed streams release theirs.
- *   - A worker thread batches continuously: every launch takes the oldest
- *     pending window of each admitted stream (windows that arrive while
- *     others are on the GPU join the next launch) and runs them as one
- *     persistent launch per format; up to max_inflight launches are queued on
- *     the server's stream.
+ *   - A worker thread batches continuously: every launch takes windows
+ *     that have arrived, of every admitted stream (windows that arrive while
+ *     others are on the GPU join the next launch; up to 96 per launch,
+ *     earliest deadline first (xcorr_server_set_deadline), each stream's in
+ *     its own order; a window longer than fold_bound samples, or of a stream
+ *     whose rows are staged zero padded, takes its stream's place in a
+ *     launch alone), and runs them as one persistent launch per format
+ *     group; up to max_inflight launches are queued on the server's stream.
+ *   - Launch configurations are tuned online: for each mix (format group and
+ *     the shapes of the admitted streams in it) every candidate (LDS-DMA
+ *     depth or register tile, 1 or 2 workgroups per CU, slices of equal cost
+ *     or equal item counts) runs 3 launches timed with events, and the one
+ *     with the most complex MACs per second of launch time is kept.  With
+ *     tune_path set, kept configurations are appended to that text file
+ *     (one "mix tile grid balance" line each) and read back when a server is
+ *     created, so a known mix starts tuned.
  *   - Each window is accumulated and dumped with reset (one integration per
  *     window); the caller keeps d_in and d_out valid until its ticket is done.
  * Results do not depend on what else is in the batch (exact int8 path).
@@ -394,6 +405,7 @@ typedef struct {
     int32_t max_streams;         /* admitted streams at once (1..64)                */
     int32_t max_inflight;        /* launches queued on the stream at once (1..8)    */
     void* stream;                /* hipStream_t for all work; NULL = null stream    */
+    const char* tune_path;       /* launch-configuration cache file, or NULL        */
 } xcorr_server_desc;
 
 typedef struct {
@@ -408,6 +420,9 @@ typedef struct {
     int32_t streams_admitted;    /* currently admitted                              */
     int32_t streams_waiting;     /* opened, waiting for memory or a slot            */
     size_t device_bytes;         /* plan memory held now                            */
+    int32_t mixes_tuned;         /* mixes whose launch configuration is settled     */
+    int32_t mixes_tuning;        /* mixes whose candidates are still being timed    */
+    int64_t deadline_misses;     /* completed windows that finished past their deadline */
 } xcorr_server_stats;
 
 /* Create a server and start its worker thread (on the current device). */
@@ -432,6 +447,19 @@ xcorr_status xcorr_server_submit(xcorr_server_t server, int32_t stream_id, const
 xcorr_status xcorr_server_poll(xcorr_server_t server, int64_t ticket, int32_t* done, xcorr_dump_info* info,
                                double* latency_ms);
 xcorr_status xcorr_server_wait(xcorr_server_t server, int64_t ticket, xcorr_dump_info* info, double* latency_ms);
+
+/* Real-time deadlines (Sec. 3: a correlator keeps up when each window is
+ * done before the next one has arrived): from now on a window of n_time
+ * samples submitted to this stream is due n_time * sample_period_s seconds
+ * after its submission (0 = no deadline, the default).  The worker orders
+ * pending windows by deadline and closes a launch before it would make a
+ * window in it late that could still be on time (a throughput model of
+ * recent launches estimates their time), so that short urgent windows do
+ * not wait behind long ones; when the most urgent window is late anyway,
+ * the launch may take twice its time (at least 0.25 ms) of later windows
+ * to catch up.  Windows without a deadline come last.  Misses are counted
+ * in the stats. */
+xcorr_status xcorr_server_set_deadline(xcorr_server_t server, int32_t stream_id, double sample_period_s);
 
 /* Close a stream: no more submits; its plan memory is released once its
  * queued windows are done, which may admit waiting streams. */

@@ -140,6 +140,13 @@ xcorr_status run_step(xcorr_batch_t b, const void* const* d_in, const int64_t* n
                       bool fused_to_acc)
 {
     const size_t np = b->plans.size();
+    // a plan may appear more than once (the server's windows of one
+    // stream) only where it reads the caller's rows as they are: staged
+    // rows would share the plan's one pad buffer
+    for (size_t k = 0; k < np; ++k)
+        for (size_t j = 0; j < k; ++j)
+            if (b->plans[j] == b->plans[k] && b->plans[k]->n_cols != b->plans[k]->d.n_inputs)
+                return fail(XCORR_ERR_UNSUPPORTED, "a plan with padded rows twice in one step");
     std::vector<int64_t> chunks(np, 0);
     int64_t rounds = 0;
     for (size_t k = 0; k < np; ++k) {

@@ -36,7 +36,8 @@ EXPORTS = ("xcorr_plan", "xcorr_accumulate", "xcorr_dump", "xcorr_accumulate_dum
            "xcorr_server_create", "xcorr_server_open", "xcorr_server_submit", "xcorr_server_poll",
            "xcorr_server_wait", "xcorr_server_close", "xcorr_server_query", "xcorr_server_destroy",
            "xcorr_corner_turn", "xcorr_dump_tiles", "xcorr_accumulate_gated", "xcorr_fstage",
-           "xcorr_fstage_work_bytes", "xcorr_clock_probe", "xcorr_correlate_noalloc")
+           "xcorr_fstage_work_bytes", "xcorr_clock_probe", "xcorr_correlate_noalloc",
+           "xcorr_server_set_deadline")
 
 
 class PlanDesc(ctypes.Structure):
@@ -68,7 +69,7 @@ class BatchConfig(ctypes.Structure):
 
 class ServerDesc(ctypes.Structure):
     _fields_ = [("device_budget", ctypes.c_size_t), ("max_streams", ctypes.c_int32),
-                ("max_inflight", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("max_inflight", ctypes.c_int32), ("stream", ctypes.c_void_p), ("tune_path", ctypes.c_char_p)]
 
 
 class ServerStats(ctypes.Structure):
@@ -76,7 +77,9 @@ class ServerStats(ctypes.Structure):
                 ("elapsed_s", ctypes.c_double), ("latency_p50_ms", ctypes.c_double),
                 ("latency_p99_ms", ctypes.c_double), ("latency_max_ms", ctypes.c_double),
                 ("mean_batch", ctypes.c_double), ("streams_admitted", ctypes.c_int32),
-                ("streams_waiting", ctypes.c_int32), ("device_bytes", ctypes.c_size_t)]
+                ("streams_waiting", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
+                ("mixes_tuned", ctypes.c_int32), ("mixes_tuning", ctypes.c_int32),
+                ("deadline_misses", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -135,6 +138,7 @@ def _load():
     L.xcorr_server_poll.argtypes = [vp, i64, P(ctypes.c_int32), P(DumpInfo), P(ctypes.c_double)]
     L.xcorr_server_wait.argtypes = [vp, i64, P(DumpInfo), P(ctypes.c_double)]
     L.xcorr_server_close.argtypes = [vp, ctypes.c_int32]
+    L.xcorr_server_set_deadline.argtypes = [vp, ctypes.c_int32, ctypes.c_double]
     L.xcorr_server_query.argtypes = [vp, P(ServerStats)]
     L.xcorr_server_destroy.argtypes = [vp]
     L.xcorr_corner_turn.argtypes = [vp, vp, P(PacketLayout), i32, vp, vp]
@@ -467,10 +471,11 @@ class Server:
     """
 
     def __init__(self, device_budget: int, max_streams: int = 16, max_inflight: int = 2,
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, tune_path: str | None = None):
         self.stream = stream if stream is not None else torch.cuda.Stream()
+        self._tune_path = tune_path.encode() if tune_path else None
         d = ServerDesc(int(device_budget), int(max_streams), int(max_inflight),
-                       ctypes.c_void_p(int(self.stream.cuda_stream)))
+                       ctypes.c_void_p(int(self.stream.cuda_stream)), self._tune_path)
         h = ctypes.c_void_p()
         _check(lib.xcorr_server_create(ctypes.byref(h), ctypes.byref(d)))
         self._h = h
@@ -518,6 +523,10 @@ class Server:
         lat = ctypes.c_double(0)
         _check(lib.xcorr_server_wait(self._h, int(ticket), ctypes.byref(info), ctypes.byref(lat)))
         return Dump(info.samples_accumulated, info.start_sample, info.n_dumps), lat.value
+
+    def set_deadline(self, sid: int, sample_period_s: float):
+        """Windows of this stream are due n_time * sample_period_s after submission."""
+        _check(lib.xcorr_server_set_deadline(self._h, int(sid), float(sample_period_s)))
 
     def close_stream(self, sid: int):
         _check(lib.xcorr_server_close(self._h, int(sid)))

@@ -156,7 +156,7 @@ def test_server_calls_on_invalid_handles_and_arguments():
     bogus = ctypes.c_void_p(0x1234)
     h = ctypes.c_void_p()
     for budget, streams, inflight in ((0, 4, 2), (1 << 30, 0, 2), (1 << 30, 65, 2), (1 << 30, 4, 0), (1 << 30, 4, 9)):
-        d = xcorr.ServerDesc(budget, streams, inflight, None)
+        d = xcorr.ServerDesc(budget, streams, inflight, None, None)
         assert L.xcorr_server_create(ctypes.byref(h), ctypes.byref(d)) == -1
         assert h.value is None
     assert L.xcorr_server_create(None, None) == -1
@@ -168,6 +168,7 @@ def test_server_calls_on_invalid_handles_and_arguments():
     assert L.xcorr_server_poll(bogus, 1, ctypes.byref(done), None, None) == -4
     assert L.xcorr_server_wait(bogus, 1, None, None) == -4
     assert L.xcorr_server_close(bogus, 1) == -4
+    assert L.xcorr_server_set_deadline(bogus, 1, 1e-3) == -4
     assert L.xcorr_server_query(bogus, None) == -4
     assert L.xcorr_server_destroy(bogus) == -4
     assert L.xcorr_server_destroy(None) == -4

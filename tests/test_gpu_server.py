@@ -152,3 +152,72 @@ def test_server_errors():
             srv.submit(sid, x, o)               # closed stream
         with pytest.raises(X.XcorrError):
             srv.poll(10 ** 9)                   # unknown ticket
+
+
+def test_server_batches_several_windows_of_a_stream_and_tunes(tmp_path):
+    # windows submitted in bursts: one launch takes several windows of the
+    # same stream (each its own fused window); the online tuner times every
+    # candidate configuration on those launches, settles, and writes the
+    # settled configuration to its cache file, which a second server reads
+    # back (it starts with the mix tuned); every result is the oracle's
+    say("server: bursts of windows, online tuning, tuning cache")
+    X = xc()
+    path = str(tmp_path / "tune.txt")
+    shapes = [(32, 6, 1024), (66, 3, 700), (128, 2, 1500)]
+    data = [windows(n, c, [t] * 4, seed=90 + n) for (n, c, t) in shapes]
+    refs = [[oracle.correlate(x.cpu().numpy(), "ci4") for x in xs] for xs in data]
+    with X.Server(device_budget=1 << 30, max_streams=8, max_inflight=1, tune_path=path) as srv:
+        sids = [srv.open(n, c) for (n, c, _) in shapes]
+        for rep in range(20):
+            outs, tks = [], []
+            for sid, xs in zip(sids, data):
+                for x in xs:
+                    o = srv.new_output(sid)
+                    outs.append(o)
+                    tks.append(srv.submit(sid, x, o))
+            for t in tks:
+                srv.wait(t)
+            k = 0
+            for si, xs in enumerate(data):
+                for j in range(len(xs)):
+                    np.testing.assert_array_equal(outs[k].cpu().numpy(), refs[si][j],
+                                                  err_msg="rep %d stream %d window %d" % (rep, si, j))
+                    k += 1
+        st = srv.stats()
+    assert st["mean_batch"] > 1.5, st
+    assert st["mixes_tuned"] >= 1, st
+    lines = open(path).read().split("\n")
+    assert any(l.strip() for l in lines)
+    with X.Server(device_budget=1 << 30, max_streams=8, tune_path=path) as srv:
+        assert srv.stats()["mixes_tuned"] >= 1
+
+
+def test_server_deadlines_order_and_count():
+    # earliest deadline first: a stream with tight deadlines beside one
+    # without; results stay the oracle's, and misses are counted against the
+    # deadlines (none are possible at a generous period, every window misses
+    # an impossible one)
+    say("server: deadlines")
+    X = xc()
+    big = windows(256, 16, [4096] * 3, seed=71)
+    small = windows(32, 4, [1024] * 6, seed=72)
+    rb = [oracle.correlate(x.cpu().numpy(), "ci4") for x in big]
+    rs = [oracle.correlate(x.cpu().numpy(), "ci4") for x in small]
+    for period, expect in ((10.0, "none"), (1e-12, "all")):
+        with X.Server(device_budget=1 << 32, max_streams=4, max_inflight=1) as srv:
+            sb, ss = srv.open(256, 16), srv.open(32, 4)
+            srv.set_deadline(ss, period)
+            ob = [srv.new_output(sb) for _ in big]
+            os_ = [srv.new_output(ss) for _ in small]
+            tks = [srv.submit(sb, x, o) for x, o in zip(big, ob)] + [srv.submit(ss, x, o) for x, o in zip(small, os_)]
+            for t in tks:
+                srv.wait(t)
+            st = srv.stats()
+        for o, r in zip(ob, rb):
+            np.testing.assert_array_equal(o.cpu().numpy(), r)
+        for o, r in zip(os_, rs):
+            np.testing.assert_array_equal(o.cpu().numpy(), r)
+        if expect == "none":
+            assert st["deadline_misses"] == 0, st
+        else:
+            assert st["deadline_misses"] == len(small), st
