@@ -85,24 +85,13 @@ typedef enum {
  * pads to 16 from 160 inputs up, where the window is bound by the matrix
  * cores; below that, rows that are a multiple of 4 (2) are read as they
  * are by the register tile.  Growing the buffer waits for the plan's
- * stream and allocates, as the 8-bit plane staging below does; xcorr_plan_bytes
- * does not count it. */
+ * stream and allocates; xcorr_plan_bytes does not count it. */
 
 /* Tile variants of the int8 path (xcorr_plan_desc.tile).  All give identical
  * (exact) results; they differ in how samples reach LDS. */
-/* With 8-bit samples a single LDS-DMA plan
- * first splits each chunk's rows into real and imaginary planes (one HBM
- * pass into a staging buffer the plan holds and grows to its largest chunk,
- * which xcorr_plan_bytes does not count).  Growing it waits for the plan's
- * stream and allocates, so a call that would grow it cannot run under
- * stream capture; one window of the largest size first avoids that.  With
- * 32 channels or more (4 per group of 8) the split of each channel group
- * runs on a second stream the plan creates on first use (with its events),
- * ordered after the work already on the plan's stream, and the kernel of
- * each group waits on the plan's stream for that group's split; the
- * calls return with all their work ordered on the plan's stream, as usual.
- * Batches of 8-bit plans use the register tile.  DMA8 takes 4-bit samples
- * only. */
+/* The LDS-DMA tiles copy rows as they are, 4-bit and 8-bit samples alike,
+ * and transpose them in LDS reads; single plans and batches use them.
+ * DMA8 takes 4-bit samples only. */
 #define XCORR_TILE_DEFAULT 0       /* LDS-DMA depth 4 where allowed, else registers */
 #define XCORR_TILE_DMA8 1          /* buffer loads straight to LDS, 8 steps in flight */
 #define XCORR_TILE_DMA4 2          /* the same, 4 steps in flight                   */
@@ -209,8 +198,8 @@ xcorr_status xcorr_destroy(xcorr_plan_t plan);
  *   d_out  device, [n_channels][n_inputs(n_inputs+1)/2][2], int64 (int32
  *          with XCORR_FLAG_OUT_I32), written completely
  * n_time must lie in [1, fold_bound] (one launch): longer windows need the
- * plan's accumulator, and are refused with XCORR_ERR_ARG.  8-bit samples
- * use the register-staged tile (the LDS-DMA tile reads a staged copy).
+ * plan's accumulator, and are refused with XCORR_ERR_ARG.  Rows of a
+ * multiple of 16 inputs take the LDS-DMA tile, others the register tile.
  * Each call clears the counters (a fill kernel) and copies the table (a
  * host-to-device copy of a table the library keeps for the process) before
  * its kernel, all on desc->stream; no hipMalloc, hipFree or other

@@ -299,85 +299,12 @@ size_t plan_device_bytes(const xcorr_plan_desc* d, size_t n_items)
     return acc + (has_acc32(d) ? acc / 2 : 0) + n_items * sizeof(WorkItem) + 256 + 32;
 }
 
-void release_side(xcorr_plan_t p)
-{
-    for (int g = 0; g <= kPlaneGroups; ++g) {
-        if (p->side_ev[g]) (void)hipEventDestroy(p->side_ev[g]);
-        p->side_ev[g] = nullptr;
-    }
-    if (p->side) (void)hipStreamDestroy(p->side);
-    p->side = nullptr;
-}
-
 // in: rows of n_cols inputs (already staged).
 xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
                           const void* src, void* dst, int mode)
 {
     LaunchArgs a = chunk_args(p, in, chan_stride, t_len, src, dst, mode);
     hipError_t e;
-    if (p->d.path == XCORR_PATH_I8_MFMA && p->d.format == XCORR_CI8 && p->tile != kTileRegs &&
-        p->n_cols % 16 == 0) {
-        // the LDS-DMA kernel reads the chunk with each row split into its
-        // real and imaginary planes: one HBM pass into the plan's staging
-        // buffer (grown to the largest chunk seen)
-        const int64_t row = staged_row_bytes(p);
-        const size_t need = (size_t)row * t_len * p->d.n_channels;
-        xcorr_status gs = grow_buffer(p, p->stream, (void**)&p->d_planes, &p->planes_bytes, need,
-                                      "8-bit plane staging");
-        if (gs != XCORR_OK) return gs;
-        // The split is an HBM pass and the kernel an MFMA-bound one: with
-        // enough channels, split the channels into groups and run the split
-        // of every group on a side stream, so that the kernel of group g
-        // runs while the later groups are being split.
-        const int cg = p->ch_group;
-        const int n_ch = p->d.n_channels;
-        bool overlap = n_ch >= 4 * kPlaneGroups * cg;
-        if (overlap && !p->side) {
-            e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
-            for (int g = 0; e == hipSuccess && g <= kPlaneGroups; ++g)
-                e = hipEventCreateWithFlags(&p->side_ev[g], hipEventDisableTiming);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                release_side(p);
-                overlap = false;
-            }
-        }
-        if (!overlap) {
-            e = launch_ci8_planes(in, chan_stride, p->n_cols, t_len, n_ch, p->d_planes, p->stream);
-            if (e != hipSuccess) return hip_fail(e, "8-bit plane split");
-            a = chunk_args(p, p->d_planes, row * t_len, t_len, src, dst, mode);
-        } else {
-            // the side stream starts after everything before this chunk on
-            // the plan's stream (the previous chunk's kernels read d_planes)
-            int c_at[kPlaneGroups + 1];
-            for (int g = 0; g <= kPlaneGroups; ++g) c_at[g] = (int)((int64_t)n_ch * g / kPlaneGroups) / cg * cg;
-            c_at[kPlaneGroups] = n_ch;
-            e = hipEventRecord(p->side_ev[kPlaneGroups], p->stream);
-            if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->side_ev[kPlaneGroups], 0);
-            for (int g = 0; e == hipSuccess && g < kPlaneGroups; ++g) {
-                e = launch_ci8_planes(in + c_at[g] * chan_stride, chan_stride, p->n_cols, t_len,
-                                      c_at[g + 1] - c_at[g], p->d_planes + c_at[g] * row * t_len, p->side);
-                if (e == hipSuccess) e = hipEventRecord(p->side_ev[g], p->side);
-            }
-            if (e != hipSuccess) return hip_fail(e, "8-bit plane split");
-            // bytes per channel of the result and of the source it adds
-            const int64_t out_ch = p->n_b * 2 * (mode == 1 ? 4 : 8);
-            const int64_t src_ch = p->n_b * 2 * (mode == 0 ? 8 : 4);
-            for (int g = 0; g < kPlaneGroups; ++g) {
-                e = hipStreamWaitEvent(p->stream, p->side_ev[g], 0);
-                if (e != hipSuccess) return hip_fail(e, "8-bit plane split: stream wait");
-                const int c0 = c_at[g], nc = c_at[g + 1] - c_at[g];
-                LaunchArgs ag = chunk_args(p, p->d_planes + c0 * row * t_len, row * t_len, t_len,
-                                           src ? (const uint8_t*)src + c0 * src_ch : nullptr,
-                                           (uint8_t*)dst + c0 * out_ch, mode);
-                ag.n_channels = nc;
-                ag.n_blocks = ag.n_items * ((nc + ag.ch_group - 1) / ag.ch_group);
-                e = launch_i8(ag, p->d.format, p->tile, p->persist_grid, p->d_counters, p->stream);
-                if (e != hipSuccess) return hip_fail(e, "X-stage kernel launch");
-            }
-            return XCORR_OK;
-        }
-    }
     switch (p->d.path) {
     case XCORR_PATH_I8_MFMA:
         e = launch_i8(a, p->d.format, p->tile, p->persist_grid, p->d_counters, p->stream);
@@ -762,11 +689,9 @@ xcorr_status xcorr_destroy(xcorr_plan_t p)
     release(p->d_items);
     release(p->d_counters);
     release(p->d_tile_sel);
-    release(p->d_planes);
     release(p->d_pad);
     release(p->d_gate_buf);
     release(p->d_gate_idx);
-    release_side(p);
     delete p;
     if (e != hipSuccess) return hip_fail(e, "destroy: stream synchronize");
     return XCORR_OK;

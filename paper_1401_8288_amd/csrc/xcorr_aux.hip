@@ -25,30 +25,6 @@ __global__ void copy_kernel(v4i* dst, const v4i* src, size_t n16, uint8_t* tail,
     if (blockIdx.x == 0 && threadIdx.x < n_tail) tail[threadIdx.x] = stail[threadIdx.x];
 }
 
-// One thread: 8 samples of one row (16 bytes in, 8 + 8 bytes out).
-__global__ void __launch_bounds__(256) ci8_planes_kernel(const uint8_t* in, int64_t chan_stride, int n_inputs,
-                                                         int64_t t_len, int n_channels, uint8_t* out)
-{
-    const int64_t per_row = n_inputs / 8;
-    const int64_t per_chan = t_len * per_row;
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= per_chan) return;
-    const int64_t t = u / per_row;
-    const int g = (int)(u - t * per_row);
-    const int64_t row = 2 * (int64_t)n_inputs;
-    for (int c = blockIdx.y; c < n_channels; c += gridDim.y) {
-        const uint4 v = *(const uint4*)(in + c * chan_stride + t * row + 16 * g);
-        // even bytes are real parts, odd bytes imaginary parts
-        const uint2 re = make_uint2(__builtin_amdgcn_perm(v.y, v.x, 0x06040200u),
-                                    __builtin_amdgcn_perm(v.w, v.z, 0x06040200u));
-        const uint2 im = make_uint2(__builtin_amdgcn_perm(v.y, v.x, 0x07050301u),
-                                    __builtin_amdgcn_perm(v.w, v.z, 0x07050301u));
-        uint8_t* o = out + ((int64_t)c * t_len + t) * row;
-        *(uint2*)(o + 8 * g) = re;
-        *(uint2*)(o + n_inputs + 8 * g) = im;
-    }
-}
-
 // out[k] = (a64 ? a64[k] : 0) + (a32 ? a32[k] : 0) over n (re, im) pairs, out
 // and a64 int64, a32 int32 (out may be a64).
 __global__ void __launch_bounds__(256) add_i32_kernel(longlong2* out, const longlong2* a64, const int2* a32, size_t n)
@@ -132,19 +108,6 @@ hipError_t launch_pad_rows(uint8_t* out, int out_row, const uint8_t* in, int in_
     const dim3 grid((unsigned)gx, n_channels < 65535 ? n_channels : 65535);
     hipLaunchKernelGGL(pad_rows_kernel, grid, dim3(256), 0, s, out, out_row, in, in_row, in_chan_stride, idx, n_rows,
                        n_channels);
-    return hipGetLastError();
-}
-
-hipError_t launch_ci8_planes(const uint8_t* in, int64_t chan_stride, int n_inputs, int64_t t_len,
-                             int n_channels, uint8_t* out, hipStream_t s)
-{
-    if (t_len <= 0 || n_channels <= 0) return hipSuccess;
-    if (n_inputs % 8) return hipErrorInvalidValue;
-    const int64_t per_chan = t_len * (n_inputs / 8);
-    const int64_t gx = (per_chan + 255) / 256;
-    if (gx > 0x7fffffff) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)gx, n_channels < 65535 ? n_channels : 65535);
-    hipLaunchKernelGGL(ci8_planes_kernel, grid, dim3(256), 0, s, in, chan_stride, n_inputs, t_len, n_channels, out);
     return hipGetLastError();
 }
 

@@ -244,7 +244,9 @@ xcorr_status check_config(xcorr_batch_t b, const xcorr_batch_config& c)
 {
     if (c.tile < 0 || c.tile > kTileRegs) return fail(XCORR_ERR_ARG, "unknown tile %d", c.tile);
     if ((c.tile == kTileDma8 || c.tile == kTileDma4) && !b->dma_ok)
-        return fail(XCORR_ERR_UNSUPPORTED, "LDS-DMA tiles need 4-bit samples in rows of 16 inputs");
+        return fail(XCORR_ERR_UNSUPPORTED, "LDS-DMA tiles need rows of a multiple of 16 inputs");
+    if (c.tile == kTileDma8 && b->format != XCORR_CI4)
+        return fail(XCORR_ERR_UNSUPPORTED, "the DMA8 tile takes 4-bit samples only");
     if (c.grid < 8 || c.grid % 8 || c.grid > 65536) return fail(XCORR_ERR_ARG, "grid must be a multiple of 8");
     if (c.balance != 0 && c.balance != 1) return fail(XCORR_ERR_ARG, "balance must be 0 or 1");
     return XCORR_OK;
@@ -285,7 +287,7 @@ xcorr_status xcorr_batch_create(xcorr_batch_t* out, const xcorr_plan_t* plans, i
         if (p->d.path != XCORR_PATH_I8_MFMA) return fail(XCORR_ERR_UNSUPPORTED, "batches use the int8 path");
         if (fmt >= 0 && p->d.format != fmt) return fail(XCORR_ERR_ARG, "plans of a batch must share the format");
         fmt = p->d.format;
-        dma_ok = dma_ok && p->d.format == XCORR_CI4 && p->n_cols % 16 == 0;
+        dma_ok = dma_ok && p->n_cols % 16 == 0;
         for (int j = 0; j < k; ++j)
             if (plans[j] == plans[k]) return fail(XCORR_ERR_ARG, "plan %d appears twice", k);
     }
@@ -362,8 +364,9 @@ xcorr_status xcorr_batch_autotune(xcorr_batch_t b, const void* const* d_in, cons
         if (p->acc_valid || p->acc32_valid || p->samples != 0)
             return fail(XCORR_ERR_STATE, "autotune needs every plan freshly reset");
     std::vector<int> tiles;
-    if (b->dma_ok) tiles = {kTileDma4, kTileDma8, kTileRegs};
-    else tiles = {kTileRegs};
+    if (!b->dma_ok) tiles = {kTileRegs};
+    else if (b->format == XCORR_CI4) tiles = {kTileDma4, kTileDma8, kTileRegs};
+    else tiles = {kTileDma4, kTileRegs};
     const int g1 = ((b->n_cu + 7) / 8) * 8;
     std::vector<xcorr_batch_config> cands;
     for (int t : tiles)

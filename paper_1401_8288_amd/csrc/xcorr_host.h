@@ -7,10 +7,6 @@
 
 #include <vector>
 
-// Channel groups of an 8-bit LDS-DMA chunk: the plane split of group g + 1
-// runs beside the kernel of group g.
-constexpr int kPlaneGroups = 8;
-
 struct xcorr_plan_s {
     xcorr_plan_desc d;
     int device = 0;
@@ -45,10 +41,6 @@ struct xcorr_plan_s {
     int persist_grid = 0;           // persistent workgroups of the LDS-DMA variants, 0 = off
     int* d_counters = nullptr;      // 8 work counters for batched launches over this plan
     uint8_t* d_tile_sel = nullptr;  // tile selection of xcorr_dump_tiles (allocated on first use)
-    uint8_t* d_planes = nullptr;    // 8-bit LDS-DMA launches: the chunk with rows split into re | im planes
-    size_t planes_bytes = 0;        // (grows on use)
-    hipStream_t side = nullptr;     // ... whose plane split runs here, a channel group ahead of the
-    hipEvent_t side_ev[kPlaneGroups + 1] = {};  // kernel (created on first use)
     void* d_gate_buf = nullptr;     // gated accumulation: packed samples of all gates (grows on use)
     size_t gate_buf_bytes = 0;
     int32_t* d_gate_idx = nullptr;  // ... and their source sample indices

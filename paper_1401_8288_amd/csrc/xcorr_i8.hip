@@ -51,15 +51,16 @@ constexpr int kPitch = 80;                 // LDS bytes per row (64 samples + 16
 // (ds_read_b64_tr_b8); no vector registers or LDS writes are spent on staging.
 // The DMA variant comes in two copy-pipeline depths (LDS buffers in flight),
 // 4 and 8; the plan's tile setting or the autotuner picks one.  V_CI8_DMA4:
-// 8-bit samples with n_inputs % 16 == 0 whose rows the host has split into
-// a real and an imaginary plane ([time][re of every input | im of every
-// input]); both planes are copied and transposed like the 4-bit bytes, and
-// their fragments are the MFMA operands as they are.
+// 8-bit samples in rows of a multiple of 16 inputs, copied as they are
+// (interleaved re, im bytes) and transposed by the 16-bit LDS transpose
+// read (ds_read_b64_tr_b16), which gives a lane one input's (re, im) pairs
+// of 4 consecutive samples; two byte permutes per dword then separate the
+// real and imaginary operands.
 enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_DMA4 = 2, V_CI4_DMA8 = 3, V_CI8_DMA4 = 4 };
 __host__ __device__ constexpr bool is_ci4(int v) { return v != V_CI8 && v != V_CI8_DMA4; }
 __host__ __device__ constexpr bool is_dma(int v) { return v == V_CI4_DMA4 || v == V_CI4_DMA8 || v == V_CI8_DMA4; }
 __host__ __device__ constexpr int dma_depth(int v) { return v == V_CI4_DMA8 ? 8 : 4; }
-// LDS-DMA copies one wave issues per step: two per sample plane.
+// LDS-DMA copies one wave issues per step (1 KB each).
 __host__ __device__ constexpr int dma_copies(int v) { return v == V_CI8_DMA4 ? 4 : 2; }
 
 // Register-staged variants: global loads run kPrefetch steps ahead of the
@@ -84,11 +85,11 @@ __device__ __forceinline__ constexpr int group_steps() { return is_dma(FMT) ? dm
 // LDS geometry.  CI4: one part per slot, the raw bytes (re and im nibbles)
 // of 64 samples x 64 inputs, rows of 64 bytes padded to kPitch.  CI8: two
 // parts, re rows and im rows.  V_CI4_DMA*: unpadded 64-byte sample rows.
-// V_CI8_DMA4: a buffer is two planes (re, then im) of V_CI4_DMA* slots.
+// V_CI8_DMA4: unpadded 128-byte sample rows (64 inputs x (re, im)).
 template <int FMT>
 struct Geo {
-    static constexpr int kParts = (FMT == V_CI8 || FMT == V_CI8_DMA4) ? 2 : 1;
-    static constexpr int kRowPitch = is_dma(FMT) ? kRowBlock : kPitch;
+    static constexpr int kParts = FMT == V_CI8 ? 2 : 1;
+    static constexpr int kRowPitch = FMT == V_CI8_DMA4 ? 2 * kRowBlock : is_dma(FMT) ? kRowBlock : kPitch;
     static constexpr int kPart = kRowBlock * kRowPitch;
     static constexpr int kSlotBytes = kParts * kPart;
     static constexpr int kBufBytes = kSlots * kSlotBytes;
@@ -218,40 +219,90 @@ struct Stager<V_CI4_DMA4> : DmaStager {};
 template <>
 struct Stager<V_CI4_DMA8> : DmaStager {};
 
-// V_CI8_DMA4 staging: the same copies for the real plane (the first
-// n_inputs bytes of a row) into the buffer's first half, and for the
-// imaginary plane (the next n_inputs bytes) into its second half.
-constexpr int kPlaneBytes = kSlots * kRowBlock * kRowBlock;
-struct DmaStager2 : DmaStager {
-    uint32_t vofs_im[2];
+// V_CI8_DMA4 staging.  A slot holds 64 sample rows of 128 bytes (64 inputs
+// x (re, im)); 16-byte chunk q (8 inputs) of row r sits at position
+// q ^ swz8(r).  A 16-bit transpose read takes, in each 16-lane group, 32
+// bytes (two chunks) of 4 consecutive rows; two groups of one pass take rows
+// 16 apart.  Rows of one parity in a pass then differ in bits 1 and 4, and
+// mapping those bits to the XOR mask's bits 1 and 2 puts the pass's chunk
+// pairs on distinct banks.  The mask does not depend on bits 2 and 3, so the
+// four reads of a fragment (rows 4 apart) share one address.  One LDS-DMA
+// instruction fills 1 KB: lane l writes 16 bytes at 16 * l, i.e. row l / 8,
+// position l % 8; the two waves of a slot copy 32 rows each in four.
+__device__ __forceinline__ int swz8(int row)
+{
+    return (((row >> 1) & 1) << 1) | (((row >> 4) & 1) << 2);
+}
+
+struct DmaStagerI {
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t vofs[4];
+    int lds_ofs;
+    int row_bytes;
 
     __device__ __forceinline__ void init(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane)
     {
-        DmaStager::init(a, w, lane);
+        row_bytes = a.row_bytes;
+        rsrc = channel_rsrc(a, w.stage_rb, w.stage_ch);
+        lds_ofs = w.stage_slot * Geo<V_CI8_DMA4>::kSlotBytes + 32 * w.stage_part * 2 * kRowBlock;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int row = 32 * w.stage_part + 16 * j + (lane >> 2);
-            const int q = (lane & 3) ^ swz(row);
-            const int input = (w.stage_rb < 0 ? 0 : w.stage_rb) * kRowBlock + 16 * q;
-            vofs_im[j] = (uint32_t)row * (uint32_t)a.row_bytes +
-                         (input < a.n_inputs ? (uint32_t)(a.n_cols + input) : 0x80000000u);
+        for (int j = 0; j < 4; ++j) {
+            const int row = 32 * w.stage_part + 8 * j + (lane >> 3);
+            const int q = (lane & 7) ^ swz8(row);
+            const int input = (w.stage_rb < 0 ? 0 : w.stage_rb) * kRowBlock + 8 * q;
+            vofs[j] = (uint32_t)row * (uint32_t)a.row_bytes + column_offset(input, a.n_inputs, 2);
         }
     }
 
+    // Copies the samples of step k into LDS buffer buf (past the chunk: zeros).
     __device__ __forceinline__ void load(uint8_t* buf, int k) const
     {
         typedef __attribute__((address_space(3))) void lds_void;
-        DmaStager::load(buf, k);
         const uint32_t step = (uint32_t)(k * kStep) * (uint32_t)row_bytes;
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc,
-                                                     (lds_void*)(buf + kPlaneBytes + lds_ofs + 16 * kRowBlock * j),
-                                                     16, (int)(vofs_im[j] + step), 0, 0, 0);
+        for (int j = 0; j < 4; ++j)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void*)(buf + lds_ofs + 8 * 2 * kRowBlock * j), 16,
+                                                     (int)(vofs[j] + step), 0, 0, 0);
     }
 };
 template <>
-struct Stager<V_CI8_DMA4> : DmaStager2 {};
+struct Stager<V_CI8_DMA4> : DmaStagerI {};
+
+// Offset of lane's first transpose read of block blk (16 inputs) of a
+// V_CI8_DMA4 slot: the 16-lane group g takes samples 16 g..16 g + 15 in
+// four reads of 4 rows (rows 16 g + 4 r + j / 4); lane j points at 8 bytes,
+// quarter j % 4 of the block's 32 bytes, of its row.
+__device__ __forceinline__ int tr16_offset(int slot, int blk, int lane)
+{
+    const int j = lane & 15;
+    const int row = 16 * (lane >> 4) + (j >> 2);
+    return slot * Geo<V_CI8_DMA4>::kSlotBytes + row * 2 * kRowBlock + 16 * ((2 * blk + ((j >> 1) & 1)) ^ swz8(row)) +
+           8 * (j & 1);
+}
+
+// The re and im operands of one V_CI8_DMA4 fragment: lane l gets input
+// l % 16's (re, im) pairs of 16 samples from four transpose reads (4 rows
+// each, 512 bytes apart), and byte permutes gather the even (re) and odd
+// (im) bytes.
+__device__ __forceinline__ void frag_tr16(const uint8_t* buf, int ofs, v4i& re, v4i& im)
+{
+    typedef short v4s __attribute__((ext_vector_type(4)));
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) v4s lds_v4s;
+    uint32_t d[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const v2i w = __builtin_bit_cast(
+            v2i, __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(buf + ofs + 4 * r * 2 * kRowBlock)));
+        d[2 * r] = (uint32_t)w.x;
+        d[2 * r + 1] = (uint32_t)w.y;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        re[k] = (int)__builtin_amdgcn_perm(d[2 * k + 1], d[2 * k], 0x06040200u);
+        im[k] = (int)__builtin_amdgcn_perm(d[2 * k + 1], d[2 * k], 0x07050301u);
+    }
+}
 
 // Operand fragment of a 16-row block: lane l holds row l % 16 and the 16
 // samples 16 * (l / 16)..+15 of the step (the same sample set for the A and
@@ -282,7 +333,7 @@ __device__ __forceinline__ int tr_offset(int slot, int blk, int lane)
     return slot * Geo<V_CI4_DMA8>::kSlotBytes + row * kRowBlock + 16 * (blk ^ swz(row)) + 8 * (j & 1);
 }
 
-// Per-lane fragment offsets of the I and J slots (V_CI4_DMA* only).
+// Per-lane fragment offsets of the I and J slots (LDS-DMA variants).
 struct FragOfs {
     int i[4], j[4];
 };
@@ -364,14 +415,8 @@ __device__ __forceinline__ void read_raw(const uint8_t* buf, int si, int sj, int
             if (need_i<KIND>(b)) r.ri[b] = frag(pI, b, lane);
             if (need_j<KIND>(b)) r.rj[b] = frag(pJ, b, lane);
         } else if constexpr (FMT == V_CI8_DMA4) {
-            if (need_i<KIND>(b)) {
-                r.o.ia[b] = frag_tr(buf, fo.i[b]);
-                r.o.ib[b] = frag_tr(buf + kPlaneBytes, fo.i[b]);
-            }
-            if (need_j<KIND>(b)) {
-                r.o.ja[b] = frag_tr(buf, fo.j[b]);
-                r.o.jb[b] = frag_tr(buf + kPlaneBytes, fo.j[b]);
-            }
+            if (need_i<KIND>(b)) frag_tr16(buf, fo.i[b], r.o.ia[b], r.o.ib[b]);
+            if (need_j<KIND>(b)) frag_tr16(buf, fo.j[b], r.o.ja[b], r.o.jb[b]);
         } else if constexpr (is_dma(FMT)) {
             if (need_i<KIND>(b)) r.ri[b] = frag_tr(buf, fo.i[b]);
             if (need_j<KIND>(b)) r.rj[b] = frag_tr(buf, fo.j[b]);
@@ -659,8 +704,8 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
     if constexpr (is_dma(FMT)) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            fo.i[b] = tr_offset(si, b, lane);
-            fo.j[b] = tr_offset(sj, b, lane);
+            fo.i[b] = FMT == V_CI8_DMA4 ? tr16_offset(si, b, lane) : tr_offset(si, b, lane);
+            fo.j[b] = FMT == V_CI8_DMA4 ? tr16_offset(sj, b, lane) : tr_offset(sj, b, lane);
         }
     }
 
@@ -1076,11 +1121,9 @@ hipError_t launch_i8_batch(const BatchArgs& ba, int fmt, int tile, int grid, hip
     // n_inputs to be a multiple of 16
     int n16 = 1;
     for (int e = 0; e < ba.n_entries; ++e) n16 &= ba.e[e].n_cols % 16 == 0;
-    // 8-bit batches stay on the register-staged kernel: the two-plane
-    // layout of V_CI8_DMA4 is made by the single-plan launch path only
-    const int v = fmt == 1 ? V_CI8 : variant_of(fmt, n16 ? 16 : 4, tile);
-    switch (v) {
+    switch (variant_of(fmt, n16 ? 16 : 4, tile)) {
     case V_CI8:      return launch_batch_variant<V_CI8>(ba, grid, s);
+    case V_CI8_DMA4: return launch_batch_variant<V_CI8_DMA4>(ba, grid, s);
     case V_CI4:      return launch_batch_variant<V_CI4>(ba, grid, s);
     case V_CI4_DMA4: return launch_batch_variant<V_CI4_DMA4>(ba, grid, s);
     default:         return launch_batch_variant<V_CI4_DMA8>(ba, grid, s);

@@ -175,10 +175,5 @@ hipError_t launch_add_i32(void* out, const void* a64, const void* a32, size_t n_
 // t < n_rows, out channels n_rows rows apart.
 hipError_t launch_pad_rows(uint8_t* out, int out_row, const uint8_t* in, int in_row, int64_t in_chan_stride,
                            const int32_t* idx, int64_t n_rows, int n_channels, hipStream_t s);
-// 8-bit samples [channel][time][input][re, im] (channel c at in + c *
-// chan_stride) -> out[channel][time][re of every input, then im of every
-// input] (rows of the same 2 n_inputs bytes); n_inputs % 8 == 0.
-hipError_t launch_ci8_planes(const uint8_t* in, int64_t chan_stride, int n_inputs, int64_t t_len,
-                             int n_channels, uint8_t* out, hipStream_t s);
 
 }  // namespace xcorr

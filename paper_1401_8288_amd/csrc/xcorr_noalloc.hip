@@ -143,14 +143,11 @@ extern "C" xcorr_status xcorr_correlate_noalloc(const xcorr_plan_desc* d, const 
     a.src = nullptr;
     a.dst = d_out;
 
-    // 8-bit samples take the register-staged tile: its LDS-DMA form reads a
-    // plane-split copy of the window, which would need a staging allocation
-    const int tile = d->format == XCORR_CI8 ? kTileRegs : kTileDefault;
     const int grid = (d->flags & XCORR_FLAG_NO_PERSIST) ? 0 : (ds.n_cu + 7) / 8 * 8;
     e = launch_fill_zero(counters, kNoallocCounterBytes, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(items, t.items.data(), t.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = launch_i8(a, d->format, tile, grid, counters, stream);
+    if (e == hipSuccess) e = launch_i8(a, d->format, kTileDefault, grid, counters, stream);
     if (e != hipSuccess) return hip_fail(e, "no-allocation window");
     return XCORR_OK;
 }

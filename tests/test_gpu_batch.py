@@ -186,6 +186,27 @@ def test_batch_register_staged_and_ci8():
         close(plans, b)
 
 
+@pytest.mark.parametrize("tile", [0, 2])
+def test_batch_8bit_lds_dma(tile):
+    # 8-bit plans whose rows are a multiple of 16 inputs (200 inputs are
+    # staged zero padded to 208) run the LDS-DMA kernel together, full value
+    # range, one of them over two chunks (70000 samples)
+    say("batch: 8-bit LDS-DMA, tile", tile)
+    subs = [(64, 3, 300), (256, 2, 129), (16, 5, 64), (200, 1, 77), (32, 2, 70000)]
+    xs = [synth.random_input(c, t, n, "ci8", seed=81 + k, lo=-128, hi=127, device=DEV)
+          for k, (n, c, t) in enumerate(subs)]
+    refs = oracle_of(xs, "ci8")
+    plans, b = make(subs, "ci8")
+    if tile:
+        b.set_config(tile=tile, grid=b.config()["grid"], balance=0)
+    outs = [p.new_output() for p in plans]
+    b.run(xs, outs)
+    torch.cuda.synchronize()
+    for k, (o, r) in enumerate(zip(outs, refs)):
+        np.testing.assert_array_equal(o.cpu().numpy(), r, err_msg="sub %d" % k)
+    close(plans, b)
+
+
 def test_batch_more_entries_than_one_launch_holds():
     say("batch: 30 plans (several launches per step)")
     subs = [(4 * (1 + k % 5), 1 + k % 3, 64 + 7 * k) for k in range(30)]

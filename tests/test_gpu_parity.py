@@ -230,8 +230,8 @@ def test_dma_tiles_on_padded_rows(tile, shape):
 @pytest.mark.parametrize("shape", [(64, 3, 1000), (512, 1, 333), (112, 5, 64), (16, 7, 129), (48, 5, 300),
                                    (192, 2, 65), (400, 2, 77)], ids=lambda s: "x".join(map(str, s)))
 def test_int8_tile_variants_8bit(tile, shape):
-    # 8-bit samples: the LDS-DMA tile (rows split into re | im planes first)
-    # and the register tile, full value range
+    # 8-bit samples: the LDS-DMA tile (interleaved rows transposed by 16-bit
+    # LDS reads) and the register tile, full value range
     n_in, n_ch, n_t = shape
     say("tile ci8", tile, shape)
     x = synth.random_input(n_ch, n_t, n_in, "ci8", seed=tile + 3 * n_in, lo=-128, hi=127, device=DEV)
@@ -240,7 +240,7 @@ def test_int8_tile_variants_8bit(tile, shape):
     np.testing.assert_array_equal(got, ref)
 
 
-def test_8bit_plan_reuses_and_grows_its_plane_staging():
+def test_8bit_dma_plan_over_windows_of_changing_length():
     # windows of growing and shrinking length through one 8-bit LDS-DMA plan
     X = xc()
     p = X.Plan(64, 3, "ci8", "i8", tile=2)
@@ -507,13 +507,13 @@ def test_int8_items_pair_diagonals_of_two_channels(fmt, tile, shape):
     p.close()
 
 
-@pytest.mark.parametrize("n_in,n_ch,n_t", [(16, 40, 70000), (32, 33, 300), (64, 128, 129)])
-def test_8bit_plane_split_runs_beside_the_kernel(n_in, n_ch, n_t):
-    # with 32 channels or more the 8-bit LDS-DMA path splits each chunk into
-    # channel groups whose re | im plane split runs on a side stream ahead
-    # of the kernel; 70000 samples make two chunks (fold bound 65535), the
-    # second adding to the first; 33 channels give uneven groups
-    say("8-bit plane split beside the kernel", n_in, n_ch, n_t)
+@pytest.mark.parametrize("n_in,n_ch,n_t", [(16, 40, 70000), (32, 33, 300), (64, 128, 129), (2048, 2, 200)])
+def test_8bit_dma_many_channels_and_chunks(n_in, n_ch, n_t):
+    # the 8-bit LDS-DMA kernel over many channels (odd counts leave the
+    # last channel group half empty), over two chunks (70000 samples pass
+    # the 65535-sample fold bound; the second chunk adds to the first) and
+    # over 32 row blocks
+    say("8-bit dma channels and chunks", n_in, n_ch, n_t)
     x = synth.random_input(n_ch, n_t, n_in, "ci8", seed=n_ch, device=DEV)
     ref = oracle.correlate(x.cpu().numpy(), "ci8")
     got, info = run(x, "ci8", "i8")
