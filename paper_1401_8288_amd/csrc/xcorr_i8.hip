@@ -280,27 +280,32 @@ __device__ __forceinline__ int tr16_offset(int slot, int blk, int lane)
            8 * (j & 1);
 }
 
-// The re and im operands of one V_CI8_DMA4 fragment: lane l gets input
-// l % 16's (re, im) pairs of 16 samples from four transpose reads (4 rows
-// each, 512 bytes apart), and byte permutes gather the even (re) and odd
-// (im) bytes.
-__device__ __forceinline__ void frag_tr16(const uint8_t* buf, int ofs, v4i& re, v4i& im)
+// The raw words of one V_CI8_DMA4 fragment: lane l gets input l % 16's
+// (re, im) pairs of 16 samples from four transpose reads (4 rows each, 512
+// bytes apart); d[0] holds samples 0-7, d[1] samples 8-15.
+__device__ __forceinline__ void frag_tr16(const uint8_t* buf, int ofs, v4i (&d)[2])
 {
     typedef short v4s __attribute__((ext_vector_type(4)));
     typedef int v2i __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) v4s lds_v4s;
-    uint32_t d[8];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const v2i w = __builtin_bit_cast(
             v2i, __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(buf + ofs + 4 * r * 2 * kRowBlock)));
-        d[2 * r] = (uint32_t)w.x;
-        d[2 * r + 1] = (uint32_t)w.y;
+        d[r >> 1][2 * (r & 1)] = w.x;
+        d[r >> 1][2 * (r & 1) + 1] = w.y;
     }
+}
+
+// Byte permutes that gather the even (re) and odd (im) bytes of a raw
+// V_CI8_DMA4 fragment into the two MFMA operands.
+__device__ __forceinline__ void split_tr16(const v4i (&d)[2], v4i& re, v4i& im)
+{
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        re[k] = (int)__builtin_amdgcn_perm(d[2 * k + 1], d[2 * k], 0x06040200u);
-        im[k] = (int)__builtin_amdgcn_perm(d[2 * k + 1], d[2 * k], 0x07050301u);
+        const uint32_t lo = (uint32_t)d[k >> 1][2 * (k & 1)], hi = (uint32_t)d[k >> 1][2 * (k & 1) + 1];
+        re[k] = (int)__builtin_amdgcn_perm(hi, lo, 0x06040200u);
+        im[k] = (int)__builtin_amdgcn_perm(hi, lo, 0x07050301u);
     }
 }
 
@@ -382,7 +387,7 @@ struct Raw<V_CI8> {
 };
 template <>
 struct Raw<V_CI8_DMA4> {
-    Ops o;
+    v4i ri[4][2], rj[4][2];
 };
 
 template <int KIND>
@@ -415,8 +420,8 @@ __device__ __forceinline__ void read_raw(const uint8_t* buf, int si, int sj, int
             if (need_i<KIND>(b)) r.ri[b] = frag(pI, b, lane);
             if (need_j<KIND>(b)) r.rj[b] = frag(pJ, b, lane);
         } else if constexpr (FMT == V_CI8_DMA4) {
-            if (need_i<KIND>(b)) frag_tr16(buf, fo.i[b], r.o.ia[b], r.o.ib[b]);
-            if (need_j<KIND>(b)) frag_tr16(buf, fo.j[b], r.o.ja[b], r.o.jb[b]);
+            if (need_i<KIND>(b)) frag_tr16(buf, fo.i[b], r.ri[b]);
+            if (need_j<KIND>(b)) frag_tr16(buf, fo.j[b], r.rj[b]);
         } else if constexpr (is_dma(FMT)) {
             if (need_i<KIND>(b)) r.ri[b] = frag_tr(buf, fo.i[b]);
             if (need_j<KIND>(b)) r.rj[b] = frag_tr(buf, fo.j[b]);
@@ -447,11 +452,14 @@ __device__ __forceinline__ void prepare(const Raw<FMT>& r, Ops& o)
                 o.ja[b] = hi16(r.rj[b]);
                 o.jb[b] = lo16(r.rj[b]);
             }
+        } else if constexpr (FMT == V_CI8_DMA4) {
+            if (need_i<KIND>(b)) split_tr16(r.ri[b], o.ia[b], o.ib[b]);
+            if (need_j<KIND>(b)) split_tr16(r.rj[b], o.ja[b], o.jb[b]);
         } else {
             if (need_i<KIND>(b)) { o.ia[b] = r.o.ia[b]; o.ib[b] = r.o.ib[b]; }
             if (need_j<KIND>(b)) { o.ja[b] = r.o.ja[b]; o.jb[b] = r.o.jb[b]; }
         }
-        if constexpr (is_ci4(FMT) && is_dma(FMT)) {
+        if constexpr (is_dma(FMT)) {
             // Keep the split in the step that read the fragments.  Without
             // these opaque copies the compiler folds the split of a group's
             // last step into the loop-carried value and redoes it at the top
@@ -549,21 +557,30 @@ __device__ __forceinline__ void schedule_step()
 {
     constexpr int nm = 4 * n_blocks<KIND>();
     if constexpr (FMT == V_CI8_DMA4) {
-        // four copies between the first MFMAs, then one pair of fragment
-        // reads after each of the next MFMAs
+        // the four copies between the first MFMAs, then the fragment reads
+        // after the next MFMAs, then the byte permutes after the rest
         constexpr int n_dsr = 4 * n_frags<KIND>();
-        constexpr int a = nm / 8 > 0 ? nm / 8 : 1;
+        constexpr int n_valu = 8 * n_frags<KIND>();
+        constexpr int a = nm / 16 > 0 ? nm / 16 : 1;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             __builtin_amdgcn_sched_group_barrier(0x008, a, 0);    // MFMA
             __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);    // VMEM (copy)
         }
-        constexpr int rest = nm - 4 * a > 0 ? nm - 4 * a : 1;
-        constexpr int rpm = (n_dsr + rest - 1) / rest;
+        constexpr int rest = nm - 4 * a > 1 ? nm - 4 * a : 2;
+        constexpr int rm = rest / 2;
+        constexpr int rpm = (n_dsr + rm - 1) / rm;
+        constexpr int vm = rest - rm;
+        constexpr int vpm = (n_valu + vm - 1) / vm;
 #pragma unroll
-        for (int m = 0; m < rest; ++m) {
+        for (int m = 0; m < rm; ++m) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x100, rpm, 0);  // DS read
+        }
+#pragma unroll
+        for (int m = 0; m < vm; ++m) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, vpm, 0);  // VALU
         }
     } else if constexpr (is_dma(FMT)) {
         constexpr int n_dsr = 2 * n_frags<KIND>();
