@@ -266,7 +266,11 @@ xcorr_status xcorr_corner_turn(const void* d_packets, const uint8_t* d_valid, co
  *   n_spectra  host, optional: receives n_spectra
  * Device pointers 16-byte aligned.  N must be 8192 and P 1 or 2
  * (XCORR_ERR_UNSUPPORTED otherwise).  fp32 arithmetic.  Enqueued on
- * `stream`; nothing is allocated.
+ * `stream`; no device memory is allocated.  With CI4 output and at least
+ * 1024 spectra the spectra go in 8 chunks, and the transpose of each chunk
+ * runs on a second stream the library keeps per device (created with its
+ * events on first use), after that chunk's transform and beside the next
+ * one; the call returns with all its work ordered on `stream`.
  * ------------------------------------------------------------------------ */
 #define XCORR_FSTAGE_CI4 0
 #define XCORR_FSTAGE_F32 1

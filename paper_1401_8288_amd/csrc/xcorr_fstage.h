@@ -15,6 +15,7 @@ struct FstageArgs {
     void* work;              // CI4: [n_spectra][n_inputs][cp] bytes, channel-fastest codes
     int32_t n_inputs, n_taps, n_spectra, chan_begin, n_chan, out_kind;
     int32_t cp;              // channels per work row (set by the launcher)
+    int32_t m_begin, m_end;  // spectra of one launch (set by the launcher)
 };
 
 // Bytes of the work buffer the CI4 output needs.

@@ -17,11 +17,14 @@
 // channels in registers for the whole run, and the next spectrum's samples
 // load while the current one is transformed.  Its 16 channels' codes go out
 // as one 16-byte store, input-major; a second, HBM-bound kernel transposes
-// them into X-stage order.  Twiddle factors are LDS tables built once per
+// them into X-stage order, chunk by chunk beside the next chunk's transform.  Twiddle factors are LDS tables built once per
 // workgroup in double precision.  fp32 arithmetic throughout; bound by VALU
 // work (about 36 flops per sample against 2.5 bytes of HBM traffic, the
 // transpose included).
 #include "xcorr_fstage.h"
+
+#include <algorithm>
+#include <mutex>
 
 namespace xcorr {
 namespace {
@@ -121,8 +124,8 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
 
     const int t = threadIdx.x;
     const int ai = blockIdx.x % a.n_inputs;
-    const int m0 = (blockIdx.x / a.n_inputs) * kSpectra;
-    const int m1 = min(m0 + kSpectra, a.n_spectra);
+    const int m0 = a.m_begin + (blockIdx.x / a.n_inputs) * kSpectra;
+    const int m1 = min(m0 + kSpectra, a.m_end);
     const int k_first = 16 * t;                  // this thread's channels k_first .. k_first + 15
     const int base = a.chan_begin & ~15;
 
@@ -268,7 +271,8 @@ __global__ void __launch_bounds__(kThreads) fstage_transpose_kernel(FstageArgs a
     // spectra vary fastest over the grid: workgroups running together touch
     // neighbouring rows of both buffers (few pages)
     int b = blockIdx.x;
-    const int m = b % a.n_spectra;  b /= a.n_spectra;
+    const int n_m = a.m_end - a.m_begin;
+    const int m = a.m_begin + b % n_m;  b /= n_m;
     const int ct = b % n_ct;
     const int at = b / n_ct;
     const int cp0 = ct * 128, a0 = at * 128;
@@ -346,18 +350,104 @@ int64_t fstage_work_bytes(int n_inputs, int64_t n_spectra, int chan_begin, int n
     return (int64_t)n_inputs * n_spectra * cp;
 }
 
+namespace {
+
+// The transpose of a chunk of spectra runs on a second stream while the next
+// chunk is transformed (the transform is bound by the vector ALU, the
+// transpose by HBM, and a CU holds two transform workgroups and a transpose
+// one at once).  One side stream and its events per device, created on first
+// use and kept for the process; enqueue sequences are serialised.
+constexpr int kChunks = 8;
+constexpr int kMaxDevices = 64;
+
+struct Side {
+    std::mutex mu;
+    bool tried = false;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[kChunks + 1] = {};
+};
+Side g_side[kMaxDevices];
+
+// The device's side stream (lock held), or null if it cannot be created.
+bool side_ready(Side& sd)
+{
+    if (sd.tried) return sd.stream != nullptr;
+    sd.tried = true;
+    hipError_t e = hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking);
+    for (int k = 0; e == hipSuccess && k <= kChunks; ++k) e = hipEventCreateWithFlags(&sd.ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        for (int k = 0; k <= kChunks; ++k)
+            if (sd.ev[k]) (void)hipEventDestroy(sd.ev[k]);
+        if (sd.stream) (void)hipStreamDestroy(sd.stream);
+        sd.stream = nullptr;
+        return false;
+    }
+    return true;
+}
+
+template <int P>
+hipError_t launch_transform(FstageArgs a, hipStream_t s)
+{
+    const int64_t blocks = (int64_t)a.n_inputs * ((a.m_end - a.m_begin + kSpectra - 1) / kSpectra);
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    return launch_p<P>(a, dim3((unsigned)blocks), s);
+}
+
+hipError_t launch_transpose(const FstageArgs& a, hipStream_t s)
+{
+    const int64_t tiles = (int64_t)((a.cp + 127) / 128) * ((a.n_inputs + 127) / 128) * (a.m_end - a.m_begin);
+    if (tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(fstage_transpose_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_fstage(FstageArgs a, hipStream_t s)
 {
     if (a.n_spectra <= 0) return hipSuccess;
     a.cp = (int32_t)((a.chan_begin + a.n_chan + 15) / 16 * 16 - (a.chan_begin & ~15));
-    const int64_t blocks = (int64_t)a.n_inputs * ((a.n_spectra + kSpectra - 1) / kSpectra);
-    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipError_t e = a.n_taps == 1 ? launch_p<1>(a, dim3((unsigned)blocks), s) : launch_p<2>(a, dim3((unsigned)blocks), s);
-    if (e != hipSuccess || a.out_kind != 0) return e;
-    const int64_t tiles = (int64_t)((a.cp + 127) / 128) * ((a.n_inputs + 127) / 128) * a.n_spectra;
-    if (tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(fstage_transpose_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, a);
-    return hipGetLastError();
+    auto transform = [&](const FstageArgs& c) {
+        return a.n_taps == 1 ? launch_transform<1>(c, s) : launch_transform<2>(c, s);
+    };
+    const int groups = (a.n_spectra + kSpectra - 1) / kSpectra;
+    int dev = 0;
+    Side* sd = nullptr;
+    if (a.out_kind == 0 && groups >= 4 * kChunks && hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices)
+        sd = &g_side[dev];
+    std::unique_lock<std::mutex> lk;
+    if (sd) {
+        lk = std::unique_lock<std::mutex>(sd->mu);
+        if (!side_ready(*sd)) {
+            lk.unlock();
+            sd = nullptr;
+        }
+    }
+    if (!sd) {
+        a.m_begin = 0;
+        a.m_end = a.n_spectra;
+        hipError_t e = transform(a);
+        if (e != hipSuccess || a.out_kind != 0) return e;
+        return launch_transpose(a, s);
+    }
+    // chunks of whole workgroup runs; the side stream starts after the work
+    // already on s and s continues after the last transpose
+    const int per = (groups + kChunks - 1) / kChunks;
+    for (int c = 0; c < kChunks; ++c) {
+        FstageArgs ac = a;
+        ac.m_begin = std::min(c * per * kSpectra, a.n_spectra);
+        ac.m_end = std::min((c + 1) * per * kSpectra, a.n_spectra);
+        if (ac.m_begin >= ac.m_end) break;
+        hipError_t e = transform(ac);
+        if (e == hipSuccess) e = hipEventRecord(sd->ev[c], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sd->stream, sd->ev[c], 0);
+        if (e == hipSuccess) e = launch_transpose(ac, sd->stream);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(sd->ev[kChunks], sd->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, sd->ev[kChunks], 0);
+    return e;
 }
 
 }  // namespace xcorr

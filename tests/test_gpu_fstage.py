@@ -217,3 +217,43 @@ def test_full_size_sampled_against_the_oracle():
         assert ok.all(), (a, m)
     del adc, out
     torch.cuda.empty_cache()
+
+
+def test_chunked_transpose_beside_the_transform():
+    # from 1024 spectra on, the transposes of 8 chunks of spectra run on a
+    # second stream beside the next chunk's transform: 1100 spectra (a
+    # ragged last chunk) with an odd channel selection, against the
+    # unchunked result of the same samples taken in two calls below the
+    # threshold (the stream continues across calls), and two such calls on
+    # two streams in flight at once
+    X = xc()
+    n_in, P, ch0, n_ch = 3, 2, 123, 700
+    n_spec = 1100
+    say("fstage chunked", n_in, n_spec)
+    adc, h = case(n_in, n_spec, P, seed=11)
+    gain = synth.fstage_gains(n_in, n_ch, h, seed=11).to(DEV)
+    hd = h.to(DEV)
+    whole = X.fstage(adc, hd, gain, ch0, n_ch)
+    k = 600                                                  # both parts below 1024 spectra
+    first = X.fstage(adc[:, :(k + P - 1) * N].contiguous(), hd, gain, ch0, n_ch)
+    second = X.fstage(adc[:, k * N:].contiguous(), hd, gain, ch0, n_ch)
+    torch.cuda.synchronize()
+    assert whole.shape == (n_ch, n_spec, n_in)
+    assert torch.equal(torch.cat([first, second], dim=1), whole)
+    s1, s2 = torch.cuda.Stream(device=DEV), torch.cuda.Stream(device=DEV)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        a = X.fstage(adc, hd, gain, ch0, n_ch)
+    with torch.cuda.stream(s2):
+        b = X.fstage(adc, hd, gain, ch0, n_ch)
+    torch.cuda.synchronize()
+    assert torch.equal(a, whole) and torch.equal(b, whole)
+    # sampled spectra against the oracle
+    a_np = adc.cpu().numpy()
+    hd64, gd = h.numpy().astype(np.float64), gain.cpu().numpy().astype(np.float64)
+    for m in (0, 511, 512, 1099):
+        frames = a_np[:, m * N:(m + P) * N]
+        v = oracle.fstage(frames, hd64, gd, N, P, ch0, n_ch, out="c128")
+        bnd = frame_bound(frames, h, P, float(np.abs(gd).max()))
+        ok, _ = check_codes(whole[:, m:m + 1].cpu().numpy(), v, bnd)
+        assert ok.all(), m
