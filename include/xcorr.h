@@ -161,12 +161,18 @@ xcorr_status xcorr_dump_tiles(xcorr_plan_t plan, void* d_out, const uint8_t* til
  * layout of xcorr_accumulate) is integrated into plans[gate[t]]; gate is a
  * HOST array of n_time bytes, each < n_gates or 0xFF (sample discarded).
  * The plans (1..64, distinct) must share n_inputs, n_channels, format and
- * stream; their paths may differ.  The samples of each gate are first packed
- * together (one HBM pass over the kept samples, into a buffer the first plan
- * holds and grows as needed: up to the window's size), then each gate with
- * samples runs as the plan's own launch over its packed rows.  Waits for the
- * plans' stream before the first launch (the sample lists are host
- * temporaries).  Dump each gate's plan with xcorr_dump. */
+ * stream; their paths may differ.  Each gate's sample indices go to the
+ * device (a list the first plan holds).  When every plan is an int8 plan
+ * whose persistent depth-4 LDS-DMA launches read the caller's rows as they
+ * are (n_inputs a multiple of 16, default or DMA4 tile, no
+ * XCORR_FLAG_NO_PERSIST, channels below 2^31 bytes), each gate runs as its
+ * plan's own launches (up to 8192 4-bit or 4096 8-bit samples each) that
+ * copy the listed rows straight from d_in; otherwise the samples of each
+ * gate are first packed together (one HBM pass over the kept samples, into
+ * a buffer the first plan holds and grows as needed: up to the window's
+ * size) and each gate runs over its packed rows.  Waits for the plans'
+ * stream before the first launch (the sample lists are host temporaries).
+ * Dump each gate's plan with xcorr_dump. */
 xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, const void* d_in, int64_t n_time,
                                     const uint8_t* gate);
 

@@ -141,6 +141,7 @@ LaunchArgs chunk_args(const xcorr_plan_s* p, const uint8_t* in, int64_t chan_str
     a.items = p->d_items;
     a.src = src;
     a.dst = dst;
+    a.rows = nullptr;
     return a;
 }
 
@@ -299,11 +300,13 @@ size_t plan_device_bytes(const xcorr_plan_desc* d, size_t n_items)
     return acc + (has_acc32(d) ? acc / 2 : 0) + n_items * sizeof(WorkItem) + 256 + 32;
 }
 
-// in: rows of n_cols inputs (already staged).
+// in: rows of n_cols inputs (already staged).  rows: the chunk's row list
+// (row_list_ok plans only), or null.
 xcorr_status launch_chunk(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride, int32_t t_len,
-                          const void* src, void* dst, int mode)
+                          const void* src, void* dst, int mode, const int32_t* rows = nullptr)
 {
     LaunchArgs a = chunk_args(p, in, chan_stride, t_len, src, dst, mode);
+    a.rows = rows;
     hipError_t e;
     switch (p->d.path) {
     case XCORR_PATH_I8_MFMA:
@@ -322,6 +325,34 @@ xcorr_status run_window(xcorr_plan_t p, const void* d_in, int64_t n_time, void* 
 }
 
 }  // namespace
+
+int xcorr::row_list_cap(const xcorr_plan_s* p, int64_t chan_bytes)
+{
+    if (p->d.path != XCORR_PATH_I8_MFMA || p->n_cols != p->d.n_inputs || p->n_cols % 16 || !p->persist_grid ||
+        p->tile == kTileRegs || p->tile == kTileDma8 || chan_bytes >= ((int64_t)1 << 31))
+        return 0;
+    return p->d.format == XCORR_CI4 ? kRowsCapCI4 : kRowsCapCI8;
+}
+
+xcorr_status xcorr::run_window_rows(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride, const int32_t* rows,
+                                    int64_t n)
+{
+    const int64_t cap = std::min<int64_t>(p->fold_bound, row_list_cap(p, chan_stride));
+    if (cap <= 0) return fail(XCORR_ERR_UNSUPPORTED, "row lists need a persistent depth-4 LDS-DMA int8 plan");
+    AccState st = acc_state(p);
+    for (int64_t t0 = 0; t0 < n; t0 += cap) {
+        const int64_t len = std::min<int64_t>(cap, n - t0);
+        const ChunkTarget t = chunk_target(p, st, len, nullptr);
+        if (t.fold) {
+            hipError_t e = fold_acc32(p, t.fold_acc_valid, p->stream);
+            if (e != hipSuccess) return hip_fail(e, "int32 accumulator fold");
+        }
+        xcorr_status s = launch_chunk(p, in, chan_stride, (int32_t)len, t.src, t.dst, t.mode, rows + t0);
+        if (s != XCORR_OK) return s;
+        set_acc_state(p, st);
+    }
+    return XCORR_OK;
+}
 
 xcorr_status xcorr::run_window_strided(xcorr_plan_t p, const uint8_t* in, int64_t chan_stride,
                                        int64_t n_time, void* final_dst, bool staged)

@@ -525,10 +525,9 @@ xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, 
         }
     }
 
-    // The samples of each gate are gathered, in time order, into one packed
-    // buffer [channel][kept sample][input] held by the first plan (gate g
-    // occupies rows off[g] .. off[g] + n[g]); then every gate's plan
-    // accumulates its rows, all gates in one batched launch per fold chunk.
+    // The sample indices of each gate, in time order, in one list (gate g
+    // at off[g] .. off[g] + cnt[g]) held by the first plan; each gate's plan
+    // then accumulates those samples.
     xcorr_plan_s* p0 = plans[0];
     std::vector<int32_t> idx;
     std::vector<int64_t> off(n_gates, 0), cnt(n_gates, 0);
@@ -547,22 +546,39 @@ xcorr_status xcorr_accumulate_gated(const xcorr_plan_t* plans, int32_t n_gates, 
         for (int64_t t = 0; t < n_time; ++t)
             if (gate[t] != 0xFF) idx[pos[gate[t]]++] = (int32_t)t;
     }
-    // rows of the packed buffer: the kernels' row width (zero padded when
-    // the plans' rows need it), so the gates' launches read it as it is
     const int64_t row = row_bytes_of(p0), prow = staged_row_bytes(p0);
-    xcorr_status gs = grow_buffer(p0, p0->stream, &p0->d_gate_buf, &p0->gate_buf_bytes,
-                                  (size_t)kept * prow * p0->d.n_channels, "gated samples");
-    if (gs == XCORR_OK)
-        gs = grow_buffer(p0, p0->stream, (void**)&p0->d_gate_idx, &p0->gate_idx_bytes, (size_t)kept * 4,
-                         "gated sample indices");
+    // Persistent depth-4 LDS-DMA int8 plans read each gate's rows where they
+    // are, through the gate's list of sample indices (its launches copy the
+    // listed rows straight into LDS); other plans read a packed copy.
+    bool listed = true;
+    for (int g = 0; g < n_gates; ++g) listed = listed && row_list_cap(plans[g], row * n_time) > 0;
+    xcorr_status gs = grow_buffer(p0, p0->stream, (void**)&p0->d_gate_idx, &p0->gate_idx_bytes, (size_t)kept * 4,
+                                  "gated sample indices");
+    if (gs == XCORR_OK && !listed)
+        gs = grow_buffer(p0, p0->stream, &p0->d_gate_buf, &p0->gate_buf_bytes, (size_t)kept * prow * p0->d.n_channels,
+                         "gated samples");
     if (gs != XCORR_OK) return gs;
     hipError_t e = hipMemcpyAsync(p0->d_gate_idx, idx.data(), (size_t)kept * 4, hipMemcpyHostToDevice, p0->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p0->stream);   // idx is a host temporary
-    if (e == hipSuccess)
-        e = prow == row ? launch_gather_rows(p0->d_gate_buf, d_in, p0->d_gate_idx, kept, n_time, row,
-                                             p0->d.n_channels, p0->stream)
-                        : launch_pad_rows((uint8_t*)p0->d_gate_buf, (int)prow, (const uint8_t*)d_in, (int)row,
-                                          row * n_time, p0->d_gate_idx, kept, p0->d.n_channels, p0->stream);
+    if (e != hipSuccess) return hip_fail(e, "gate indices");
+    if (listed) {
+        for (int g = 0; g < n_gates; ++g) {
+            if (cnt[g] == 0) continue;
+            st = run_window_rows(plans[g], (const uint8_t*)d_in, row * n_time, p0->d_gate_idx + off[g], cnt[g]);
+            if (st != XCORR_OK) return st;
+        }
+        for (int g = 0; g < n_gates; ++g) {
+            plans[g]->samples += cnt[g];
+            plans[g]->total += cnt[g];
+        }
+        return XCORR_OK;
+    }
+    // rows of the packed buffer: the kernels' row width (zero padded when
+    // the plans' rows need it), so the gates' launches read it as it is
+    e = prow == row ? launch_gather_rows(p0->d_gate_buf, d_in, p0->d_gate_idx, kept, n_time, row, p0->d.n_channels,
+                                         p0->stream)
+                    : launch_pad_rows((uint8_t*)p0->d_gate_buf, (int)prow, (const uint8_t*)d_in, (int)row,
+                                      row * n_time, p0->d_gate_idx, kept, p0->d.n_channels, p0->stream);
     if (e != hipSuccess) return hip_fail(e, "gate gather");
 
     // One launch (per fold chunk) per gate, each over all channels: a gate

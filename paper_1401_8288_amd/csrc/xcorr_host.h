@@ -110,6 +110,16 @@ int64_t fold_bound_of(const xcorr_plan_desc* d);
 // staged: in already has rows of n_cols inputs (no padding pass).
 xcorr_status run_window_strided(xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, int64_t n_time,
                                 void* final_dst, bool staged = false);
+// Most samples one launch of this plan may take through a row list (0: the
+// plan cannot take row lists: they need a persistent depth-4 LDS-DMA int8
+// plan reading the caller's rows as they are, and channels of chan_bytes <
+// 2^31 bytes).
+int row_list_cap(const xcorr_plan_s* p, int64_t chan_bytes);
+// Accumulates the n samples of every channel whose rows are listed in rows
+// (device, int32 row indices into the rows from in, channel c's at in + c *
+// chan_stride), in launches of at most row_list_cap samples.
+xcorr_status run_window_rows(xcorr_plan_s* p, const uint8_t* in, int64_t chan_stride, const int32_t* rows,
+                             int64_t n);
 // Inputs per row the kernels of a plan with this descriptor read.
 int cols_of(const xcorr_plan_desc* d);
 // Relative cost of a work item (MFMA blocks its waves own).

@@ -56,12 +56,23 @@ constexpr int kPitch = 80;                 // LDS bytes per row (64 samples + 16
 // read (ds_read_b64_tr_b16), which gives a lane one input's (re, im) pairs
 // of 4 consecutive samples; two byte permutes per dword then separate the
 // real and imaginary operands.
-enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_DMA4 = 2, V_CI4_DMA8 = 3, V_CI8_DMA4 = 4 };
-__host__ __device__ constexpr bool is_ci4(int v) { return v != V_CI8 && v != V_CI8_DMA4; }
-__host__ __device__ constexpr bool is_dma(int v) { return v == V_CI4_DMA4 || v == V_CI4_DMA8 || v == V_CI8_DMA4; }
+// V_CI4_DMA4L, V_CI8_DMA4L: the same as V_CI4_DMA4, V_CI8_DMA4 for launches
+// with a row list (LaunchArgs.rows), whose copies read listed rows.
+enum Variant { V_CI4 = 0, V_CI8 = 1, V_CI4_DMA4 = 2, V_CI4_DMA8 = 3, V_CI8_DMA4 = 4, V_CI4_DMA4L = 5, V_CI8_DMA4L = 6 };
+__host__ __device__ constexpr bool is_listed(int v) { return v == V_CI4_DMA4L || v == V_CI8_DMA4L; }
+// The variant whose layout and fragments a variant uses.
+__host__ __device__ constexpr int base_of(int v)
+{
+    return v == V_CI4_DMA4L ? V_CI4_DMA4 : v == V_CI8_DMA4L ? V_CI8_DMA4 : v;
+}
+__host__ __device__ constexpr bool is_ci4(int v) { return base_of(v) != V_CI8 && base_of(v) != V_CI8_DMA4; }
+__host__ __device__ constexpr bool is_dma(int v)
+{
+    return base_of(v) == V_CI4_DMA4 || base_of(v) == V_CI4_DMA8 || base_of(v) == V_CI8_DMA4;
+}
 __host__ __device__ constexpr int dma_depth(int v) { return v == V_CI4_DMA8 ? 8 : 4; }
 // LDS-DMA copies one wave issues per step (1 KB each).
-__host__ __device__ constexpr int dma_copies(int v) { return v == V_CI8_DMA4 ? 4 : 2; }
+__host__ __device__ constexpr int dma_copies(int v) { return base_of(v) == V_CI8_DMA4 ? 4 : 2; }
 
 // Register-staged variants: global loads run kPrefetch steps ahead of the
 // step they feed: a channel's first reader waits for HBM, and the other
@@ -89,7 +100,7 @@ __device__ __forceinline__ constexpr int group_steps() { return is_dma(FMT) ? dm
 template <int FMT>
 struct Geo {
     static constexpr int kParts = FMT == V_CI8 ? 2 : 1;
-    static constexpr int kRowPitch = FMT == V_CI8_DMA4 ? 2 * kRowBlock : is_dma(FMT) ? kRowBlock : kPitch;
+    static constexpr int kRowPitch = base_of(FMT) == V_CI8_DMA4 ? 2 * kRowBlock : is_dma(FMT) ? kRowBlock : kPitch;
     static constexpr int kPart = kRowBlock * kRowPitch;
     static constexpr int kSlotBytes = kParts * kPart;
     static constexpr int kBufBytes = kSlots * kSlotBytes;
@@ -268,6 +279,70 @@ struct DmaStagerI {
 template <>
 struct Stager<V_CI8_DMA4> : DmaStagerI {};
 
+// Row lists (LaunchArgs.rows, the listed variants): the workgroup copies the
+// chunk's list into an LDS table when the launch starts, and the copies of
+// step k read row rows[64 k + r] of the window for the step's row r.  The
+// channel's buffer range is all of its rows (chan_stride bytes).
+template <int FMT>
+__device__ __forceinline__ int32_t* lds_rows()
+{
+    static_assert(is_listed(FMT), "row tables of the listed variants");
+    __shared__ int32_t tbl[base_of(FMT) == V_CI8_DMA4 ? kRowsCapCI8 : kRowsCapCI4];
+    return tbl;
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t listed_rsrc(const LaunchArgs& a, int rb, int ch)
+{
+    const bool ok = rb >= 0 && ch < a.n_channels;
+    const uint8_t* base = a.in + (ok ? (int64_t)ch * a.chan_stride : 0);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, ok ? (int)a.chan_stride : 0, kRsrcConfig);
+}
+
+// The copy stagers above with the step's rows looked up in the table: S is
+// the base stager, R the rows one LDS-DMA instruction spans per lane group
+// (16 for 64-byte rows, 8 for 128-byte rows).
+template <int FMT, class S, int R>
+struct ListedStager : S {
+    const int32_t* tbl;
+    int t_len;
+    int row0;                      // this lane's first row of a step
+
+    __device__ __forceinline__ void init(const LaunchArgs& a, const WaveJobT<kWaves>& w, int lane)
+    {
+        S::init(a, w, lane);
+        this->rsrc = listed_rsrc(a, w.stage_rb, w.stage_ch);
+        tbl = lds_rows<FMT>();
+        t_len = a.t_len;
+        row0 = 32 * w.stage_part + lane / (64 / R);
+        // the base stager's offsets hold row * row_bytes + column: keep the columns
+#pragma unroll
+        for (int j = 0; j < (int)(sizeof(S::vofs) / sizeof(uint32_t)); ++j) {
+            const uint32_t o = this->vofs[j];
+            this->vofs[j] = o >= 0x80000000u ? 0x80000000u : o - (uint32_t)(row0 + R * j) * (uint32_t)a.row_bytes;
+        }
+    }
+
+    __device__ __forceinline__ void load(uint8_t* buf, int k) const
+    {
+        typedef __attribute__((address_space(3))) void lds_void;
+        constexpr int n = sizeof(S::vofs) / sizeof(uint32_t);
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            const int smp = k * kStep + row0 + R * j;
+            const uint32_t col = this->vofs[j];
+            const uint32_t ofs = (smp >= t_len || col == 0x80000000u)
+                                     ? 0x80000000u
+                                     : (uint32_t)tbl[smp] * (uint32_t)this->row_bytes + col;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(this->rsrc, (lds_void*)(buf + this->lds_ofs + 64 * R * (n == 2 ? 1 : 2) * j),
+                                                     16, (int)ofs, 0, 0, 0);
+        }
+    }
+};
+template <>
+struct Stager<V_CI4_DMA4L> : ListedStager<V_CI4_DMA4L, DmaStager, 16> {};
+template <>
+struct Stager<V_CI8_DMA4L> : ListedStager<V_CI8_DMA4L, DmaStagerI, 8> {};
+
 // Offset of lane's first transpose read of block blk (16 inputs) of a
 // V_CI8_DMA4 slot: the 16-lane group g takes samples 16 g..16 g + 15 in
 // four reads of 4 rows (rows 16 g + 4 r + j / 4); lane j points at 8 bytes,
@@ -389,6 +464,10 @@ template <>
 struct Raw<V_CI8_DMA4> {
     v4i ri[4][2], rj[4][2];
 };
+template <>
+struct Raw<V_CI4_DMA4L> : Raw<V_CI4_DMA4> {};
+template <>
+struct Raw<V_CI8_DMA4L> : Raw<V_CI8_DMA4> {};
 
 template <int KIND>
 __device__ __forceinline__ constexpr bool same_block(int)
@@ -419,7 +498,7 @@ __device__ __forceinline__ void read_raw(const uint8_t* buf, int si, int sj, int
         if constexpr (FMT == V_CI4) {
             if (need_i<KIND>(b)) r.ri[b] = frag(pI, b, lane);
             if (need_j<KIND>(b)) r.rj[b] = frag(pJ, b, lane);
-        } else if constexpr (FMT == V_CI8_DMA4) {
+        } else if constexpr (base_of(FMT) == V_CI8_DMA4) {
             if (need_i<KIND>(b)) frag_tr16(buf, fo.i[b], r.ri[b]);
             if (need_j<KIND>(b)) frag_tr16(buf, fo.j[b], r.rj[b]);
         } else if constexpr (is_dma(FMT)) {
@@ -452,7 +531,7 @@ __device__ __forceinline__ void prepare(const Raw<FMT>& r, Ops& o)
                 o.ja[b] = hi16(r.rj[b]);
                 o.jb[b] = lo16(r.rj[b]);
             }
-        } else if constexpr (FMT == V_CI8_DMA4) {
+        } else if constexpr (base_of(FMT) == V_CI8_DMA4) {
             if (need_i<KIND>(b)) split_tr16(r.ri[b], o.ia[b], o.ib[b]);
             if (need_j<KIND>(b)) split_tr16(r.rj[b], o.ja[b], o.jb[b]);
         } else {
@@ -556,7 +635,7 @@ template <int FMT, int KIND>
 __device__ __forceinline__ void schedule_step()
 {
     constexpr int nm = 4 * n_blocks<KIND>();
-    if constexpr (FMT == V_CI8_DMA4) {
+    if constexpr (base_of(FMT) == V_CI8_DMA4) {
         // the four copies between the first MFMAs, then the fragment reads
         // after the next MFMAs, then the byte permutes after the rest
         constexpr int n_dsr = 4 * n_frags<KIND>();
@@ -721,8 +800,8 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJobT<kWa
     if constexpr (is_dma(FMT)) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            fo.i[b] = FMT == V_CI8_DMA4 ? tr16_offset(si, b, lane) : tr_offset(si, b, lane);
-            fo.j[b] = FMT == V_CI8_DMA4 ? tr16_offset(sj, b, lane) : tr_offset(sj, b, lane);
+            fo.i[b] = base_of(FMT) == V_CI8_DMA4 ? tr16_offset(si, b, lane) : tr_offset(si, b, lane);
+            fo.j[b] = base_of(FMT) == V_CI8_DMA4 ? tr16_offset(sj, b, lane) : tr_offset(sj, b, lane);
         }
     }
 
@@ -1033,6 +1112,11 @@ __global__ void __launch_bounds__(kThreads, 1) xcorr_i8_persist_kernel(BatchArgs
     const int hi = ba.xcd_map ? ba.slice[q + 1] : ba.slice[8];
     int* counter = ba.counters + q;
     if (threadIdx.x == 0) s_claim = lo + atomicAdd(counter, 1);
+    if constexpr (is_listed(FMT)) {
+        // a row-list launch (one entry): its list into the LDS table
+        int32_t* tbl = lds_rows<FMT>();
+        for (int i = threadIdx.x; i < ba.e[0].t_len; i += kThreads) tbl[i] = ba.e[0].rows[i];
+    }
     __syncthreads();
     int g = __builtin_amdgcn_readfirstlane(s_claim);
     if (g >= hi) {
@@ -1120,6 +1204,15 @@ int variant_of(int fmt, int n_cols, int tile)
 
 hipError_t launch_i8(const LaunchArgs& a, int fmt, int tile, int persist_grid, int* counters, hipStream_t s)
 {
+    if (a.rows) {
+        // row lists: persistent launches of the depth-4 LDS-DMA variants
+        const int v = variant_of(fmt, a.n_cols, tile);
+        if (!persist_grid || (v != V_CI4_DMA4 && v != V_CI8_DMA4) ||
+            a.t_len > (v == V_CI8_DMA4 ? kRowsCapCI8 : kRowsCapCI4) || a.chan_stride >= ((int64_t)1 << 31))
+            return hipErrorInvalidValue;
+        return v == V_CI4_DMA4 ? launch_persist_single<V_CI4_DMA4L>(a, persist_grid, counters, s)
+                               : launch_persist_single<V_CI8_DMA4L>(a, persist_grid, counters, s);
+    }
     switch (variant_of(fmt, a.n_cols, tile)) {
     case V_CI8:      return launch_variant<V_CI8>(a, s);
     case V_CI4:      return launch_variant<V_CI4>(a, s);

@@ -73,7 +73,17 @@ struct LaunchArgs {
     const WorkItem* items;
     const void* src;               // optional accumulator to add (same layout as dst)
     void* dst;                     // result: [channel][tri][2]
+    // null: the chunk's samples are rows 0 .. t_len - 1 from `in`.  Else
+    // (persistent single-entry launches of the depth-4 LDS-DMA variants
+    // only): sample k is row rows[k] from `in`, chan_stride bytes per
+    // channel cover every row named, t_len <= kRowsCap of the format.
+    const int32_t* rows;
 };
+
+// Most rows a launch with a row list takes (its LDS table: 32 KB beside the
+// 4-bit variant's 64 KB of copy buffers, 16 KB beside the 8-bit one's 128 KB).
+constexpr int kRowsCapCI4 = 8192;
+constexpr int kRowsCapCI8 = 4096;
 
 // Maps the hardware workgroup id to a work item.  Consecutive workgroup ids
 // are dispatched round-robin over the 8 XCDs; giving each XCD a contiguous

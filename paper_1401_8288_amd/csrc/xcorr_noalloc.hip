@@ -142,6 +142,7 @@ extern "C" xcorr_status xcorr_correlate_noalloc(const xcorr_plan_desc* d, const 
     a.items = items;
     a.src = nullptr;
     a.dst = d_out;
+    a.rows = nullptr;
 
     const int grid = (d->flags & XCORR_FLAG_NO_PERSIST) ? 0 : (ds.n_cu + 7) / 8 * 8;
     e = launch_fill_zero(counters, kNoallocCounterBytes, stream);

@@ -63,6 +63,35 @@ def test_gated_accumulation_matches_oracle(n_in, fmt):
         p.close()
 
 
+@pytest.mark.parametrize("fmt,flags,tile", [("ci4", 0, 0), ("ci8", 0, 0), ("ci4", "np", 0), ("ci4", 0, 3),
+                                             ("ci4", "i32", 0)])
+def test_gates_read_listed_rows_or_a_packed_copy(fmt, flags, tile):
+    # persistent depth-4 LDS-DMA plans copy each gate's rows straight from
+    # the window through the gate's row list, in launches of at most 8192
+    # (4-bit) or 4096 (8-bit) rows; other plans (no persistent launch, the
+    # register tile) read a packed copy.  A 20000-sample window whose first
+    # gate takes most samples makes several row-list launches.  The results
+    # are the oracle's either way.
+    X = xc()
+    fl = {0: 0, "np": X.FLAG_NO_PERSIST, "i32": X.FLAG_OUT_I32}[flags]
+    say("gating: listed rows", fmt, flags, tile)
+    n_in, n_ch, n_t = 64, 3, 20000
+    x = synth.random_input(n_ch, n_t, n_in, fmt, seed=41, lo=-128 if fmt == "ci8" else -8,
+                           hi=127 if fmt == "ci8" else 7, device=DEV)
+    g = np.where(np.arange(n_t) % 7 == 3, 1, 0).astype(np.uint8)
+    g[np.arange(n_t) % 11 == 5] = 255
+    plans = [X.Plan(n_in, n_ch, fmt, "i8", flags=fl, tile=tile) for _ in range(2)]
+    X.accumulate_gated(plans, x, g)
+    a = x.cpu().numpy()
+    for k, p in enumerate(plans):
+        out, info = p.dump()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy().astype(np.int64), oracle.correlate(a[:, g == k], fmt),
+                                      err_msg="gate %d" % k)
+        assert info.samples_accumulated == int((g == k).sum())
+        p.close()
+
+
 def test_gates_may_run_different_paths():
     # CI4 products summed over 3000 samples stay below 2^24: the float paths
     # are exact here

@@ -433,6 +433,17 @@ def test_large_n_workload_sampled_rows():
             np.testing.assert_array_equal(got[c, a:b], oracle.correlate_rows(x_np, w.fmt, c, r0, rc))
     say("large-N beam-power identity on all channels")
     _beam_check(x_np, w.fmt, got, seeds=(301,))
+    del got
+    # the configuration the benchmark's large-N line times: int32 output
+    say("large-N int32 output")
+    got32, info = run(x, w.fmt, "i8", flags=xc().FLAG_OUT_I32)
+    assert info.samples_accumulated == w.n_time and got32.dtype == np.int32
+    for c in (0, 99, w.n_channels - 1):
+        for r0, rc in ((0, 3), (777, 2), (2045, 3)):
+            a = r0 * (r0 + 1) // 2
+            b = (r0 + rc) * (r0 + rc + 1) // 2
+            np.testing.assert_array_equal(got32[c, a:b].astype(np.int64), oracle.correlate_rows(x_np, w.fmt, c, r0, rc))
+    _beam_check(x_np, w.fmt, got32, seeds=(302,))
     del x
     torch.cuda.empty_cache()
 
