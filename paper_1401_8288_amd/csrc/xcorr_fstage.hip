@@ -188,11 +188,18 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
 
         // ---- pass 1 over n2 (thread t = n_lo), twiddle W4096^(n_lo k0)
         dft16(v);
+        // the twiddles are read before the barrier, so that their latency
+        // overlaps the wait (the float-output kernel has no registers for it)
+        float2 tw[16];
+        if constexpr (OUT == 0) {
+#pragma unroll
+            for (int k0 = 1; k0 < 16; ++k0) tw[k0] = T1[k0 * 256 + t];
+        }
         lds_barrier();                           // previous transform's reads of L are done
 #pragma unroll
         for (int k0 = 0; k0 < 16; ++k0) {
             const float2 y = v[slot_of(k0)];
-            L[k0 * kRow + t] = k0 ? cmul(y, T1[k0 * 256 + t]) : y;
+            L[k0 * kRow + t] = k0 ? cmul(y, OUT == 0 ? tw[k0] : T1[k0 * 256 + t]) : y;
         }
         lds_barrier();
         // ---- pass 2 over n1 (thread = (k0, n0)), twiddle W256^(n0 k1)
@@ -201,11 +208,16 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
 #pragma unroll
             for (int n1 = 0; n1 < 16; ++n1) v[n1] = L[k0 * kRow + 16 * n1 + n0];
             dft16(v);
+            float2 tw2[16];
+            if constexpr (OUT == 0) {
+#pragma unroll
+                for (int k1 = 1; k1 < 16; ++k1) tw2[k1] = T2[k1 * 16 + n0];
+            }
             lds_barrier();
 #pragma unroll
             for (int k1 = 0; k1 < 16; ++k1) {
                 const float2 y = v[slot_of(k1)];
-                L[k0 * kRow + 17 * k1 + n0] = k1 ? cmul(y, T2[k1 * 16 + n0]) : y;
+                L[k0 * kRow + 17 * k1 + n0] = k1 ? cmul(y, OUT == 0 ? tw2[k1] : T2[k1 * 16 + n0]) : y;
             }
         }
         lds_barrier();
@@ -226,12 +238,15 @@ __global__ void __launch_bounds__(kThreads, 2) fstage_kernel(FstageArgs a)
         // ---- real split, equalise, requantise this thread's channels
         if (writes) {
             uint32_t q[4] = {0, 0, 0, 0};
+            // Z[-k] for k = 16 t + j sits at 4351 - 17 t - j (j > 0) and
+            // at 4352 - 17 t (j = 0, t > 0) of the padded layout
+            const float2* zc_lo = L + (4336 - 17 * t);
+            const int zc0 = t ? 4352 - 17 * t : 0;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int k = k_first + j;
-                const int kk = (4096 - k) & 4095;
                 const float2 zk = L[k + (k >> 4)];
-                const float2 zc = L[kk + (kk >> 4)];
+                const float2 zc = j ? zc_lo[15 - j] : L[zc0];
                 // X = (s - i W8192^k d) / 2 with s = Z[k] + conj Z[-k] and
                 // d = Z[k] - conj Z[-k] (the even- and odd-sample transforms)
                 const float sx = zk.x + zc.x, sy = zk.y - zc.y, dx = zk.x - zc.x, dy = zk.y + zc.y;
