@@ -85,8 +85,8 @@ def time_path(torch, xcorr, x, w, path, steps, warmup, flags=0, per_step=None, c
 def time_accumulate(torch, xcorr, x, w, steps, warmup):
     """Average ms of xcorr_accumulate alone into an int64 plan: every window
     adds into the plan's int32 accumulator (read and written), which is
-    folded into the int64 one before it passes 65535 samples; with 4096-
-    sample windows the timed steps include that fold once every 16 windows."""
+    folded into the int64 one before its sums could overflow (after
+    16777215 samples of 4-bit data, 65535 of 8-bit data)."""
     p = xcorr.Plan(w.n_inputs, w.n_channels, w.fmt, "i8")
     for _ in range(warmup):
         p.accumulate(x)
@@ -603,6 +603,9 @@ def main():
     tops64 = 8 * cmac / (ms64 * 1e-3) / 1e12
     log("int8, int64 out: %.3f ms/window, %.1f%% of int8 peak" % (ms64, 100 * tops64 / PEAK_INT8_TOPS))
     acc_steps = max(16, 65536 // w.n_time)
+    # the int32 accumulator's bound (4-bit: 2 * 8 * 8 per sample, 8-bit: 2 * 128 * 128)
+    acc_bound = 16777215 if w.fmt == "ci4" else 65535
+    acc_folds = acc_steps // max(1, acc_bound // w.n_time)
     ms_acc = time_accumulate(torch, xcorr, x, w, acc_steps, 1)
     log("int8, accumulate only (int64 accumulator): %.3f ms/window" % ms_acc)
 
@@ -627,8 +630,9 @@ def main():
         "accumulate_only": {"ms_per_step": round(ms_acc, 4),
                             "pct_int8_peak": round(100 * 8 * cmac / (ms_acc * 1e-3) / 1e12 / PEAK_INT8_TOPS, 2),
                             "steps": acc_steps,
+                            "folds_in_timed_steps": acc_folds,
                             "note": "xcorr_accumulate of an int64 plan: int32 accumulator read and written per "
-                                    "window, folded into the int64 one every 65535 samples (once in the timed steps)"},
+                                    "window, folded into the int64 one every %d samples" % acc_bound},
         "roofline": {"bound": "mfma",
                      "kernel": "xcorr_i8_persist_kernel<V_%s_DMA4, int32 out>" % w.fmt.upper(),
                      "achieved": round(tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
