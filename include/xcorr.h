@@ -274,9 +274,11 @@ xcorr_status xcorr_corner_turn(const void* d_packets, const uint8_t* d_valid, co
  * (XCORR_ERR_UNSUPPORTED otherwise).  fp32 arithmetic.  Enqueued on
  * `stream`; no device memory is allocated.  With CI4 output and at least
  * 1024 spectra the spectra go in 8 chunks, and the transpose of each chunk
- * runs on a second stream the library keeps per device (created with its
- * events on first use), after that chunk's transform and beside the next
- * one; the call returns with all its work ordered on `stream`.
+ * runs on a second stream, after that chunk's transform and beside the next
+ * one; the call returns with all its work ordered on `stream`.  The library
+ * keeps one such stream (with its events) per device and caller stream,
+ * created on first use; past 16 caller streams on a device the chunks of a
+ * call run in order on `stream`.
  * ------------------------------------------------------------------------ */
 #define XCORR_FSTAGE_CI4 0
 #define XCORR_FSTAGE_F32 1

@@ -370,24 +370,36 @@ namespace {
 // The transpose of a chunk of spectra runs on a second stream while the next
 // chunk is transformed (the transform is bound by the vector ALU, the
 // transpose by HBM, and a CU holds two transform workgroups and a transpose
-// one at once).  One side stream and its events per device, created on first
-// use and kept for the process; enqueue sequences are serialised.
+// one at once).  Each caller stream gets a side stream and events of its own
+// (per device, created on first use and kept for the process), so that
+// calls on different caller streams never wait for each other through a
+// shared side stream; past kMaxSides caller streams on a device, or if one
+// cannot be created, a call runs its chunks in order on the caller's stream.
+// Enqueue sequences on a device are serialised.
 constexpr int kChunks = 8;
 constexpr int kMaxDevices = 64;
+constexpr int kMaxSides = 16;
 
 struct Side {
-    std::mutex mu;
-    bool tried = false;
+    hipStream_t caller = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t ev[kChunks + 1] = {};
 };
-Side g_side[kMaxDevices];
+struct DeviceSides {
+    std::mutex mu;
+    int n = 0;
+    Side side[kMaxSides];
+};
+DeviceSides g_sides[kMaxDevices];
 
-// The device's side stream (lock held), or null if it cannot be created.
-bool side_ready(Side& sd)
+// The side stream of caller stream s (lock held), or null.
+Side* side_of(DeviceSides& d, hipStream_t s)
 {
-    if (sd.tried) return sd.stream != nullptr;
-    sd.tried = true;
+    for (int i = 0; i < d.n; ++i)
+        if (d.side[i].caller == s) return &d.side[i];
+    if (d.n == kMaxSides) return nullptr;
+    Side sd;
+    sd.caller = s;
     hipError_t e = hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking);
     for (int k = 0; e == hipSuccess && k <= kChunks; ++k) e = hipEventCreateWithFlags(&sd.ev[k], hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -395,10 +407,10 @@ bool side_ready(Side& sd)
         for (int k = 0; k <= kChunks; ++k)
             if (sd.ev[k]) (void)hipEventDestroy(sd.ev[k]);
         if (sd.stream) (void)hipStreamDestroy(sd.stream);
-        sd.stream = nullptr;
-        return false;
+        return nullptr;
     }
-    return true;
+    d.side[d.n] = sd;
+    return &d.side[d.n++];
 }
 
 template <int P>
@@ -429,15 +441,12 @@ hipError_t launch_fstage(FstageArgs a, hipStream_t s)
     const int groups = (a.n_spectra + kSpectra - 1) / kSpectra;
     int dev = 0;
     Side* sd = nullptr;
-    if (a.out_kind == 0 && groups >= 4 * kChunks && hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices)
-        sd = &g_side[dev];
     std::unique_lock<std::mutex> lk;
-    if (sd) {
-        lk = std::unique_lock<std::mutex>(sd->mu);
-        if (!side_ready(*sd)) {
-            lk.unlock();
-            sd = nullptr;
-        }
+    if (a.out_kind == 0 && groups >= 4 * kChunks && hipGetDevice(&dev) == hipSuccess && dev >= 0 &&
+        dev < kMaxDevices) {
+        lk = std::unique_lock<std::mutex>(g_sides[dev].mu);
+        sd = side_of(g_sides[dev], s);
+        if (!sd) lk.unlock();
     }
     if (!sd) {
         a.m_begin = 0;
