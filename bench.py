@@ -556,6 +556,8 @@ def main():
     ap.add_argument("--trace-skip", type=int, default=0, help="dispatches of each kernel left out first")
     ap.add_argument("--trace-take", type=int, default=0, help="dispatches averaged after those (0: all)")
     ap.add_argument("--trace-match", default="", help="only kernels whose name contains this")
+    ap.add_argument("--many-small-only", action="store_true",
+                    help="run only the many-small-arrays leg (for profiling its launches); prints its JSON")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary)
@@ -570,6 +572,13 @@ def main():
 
     import torch
     from paper_1401_8288_amd import synth, xcorr
+
+    if args.many_small_only:
+        # 3 + 20 batched steps, then 3 + 20 steps of one launch per plan,
+        # then the server at each speed for --serving-seconds (0: none)
+        sp = [40.0, 200.0, 400.0, 800.0] if args.serving_seconds > 0 else []
+        print(json.dumps(many_small_leg(torch, xcorr, args.serving_seconds, sp, inflight=args.serving_inflight)))
+        return
 
     dev = torch.device("cuda:0")
     w = synth.WORKLOADS[args.workload]

@@ -208,8 +208,8 @@ def test_batch_8bit_lds_dma(tile):
 
 
 def test_batch_more_entries_than_one_launch_holds():
-    say("batch: 30 plans (several launches per step)")
-    subs = [(4 * (1 + k % 5), 1 + k % 3, 64 + 7 * k) for k in range(30)]
+    say("batch: 60 plans (two launches per step; a batch holds up to 64)")
+    subs = [(4 * (1 + k % 5), 1 + k % 3, 64 + 7 * k) for k in range(60)]
     xs = inputs(subs, seed=61)
     refs = oracle_of(xs)
     plans, b = make(subs)

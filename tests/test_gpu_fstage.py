@@ -257,3 +257,36 @@ def test_chunked_transpose_beside_the_transform():
         bnd = frame_bound(frames, h, P, float(np.abs(gd).max()))
         ok, _ = check_codes(whole[:, m:m + 1].cpu().numpy(), v, bnd)
         assert ok.all(), m
+
+
+def test_chunked_calls_on_many_streams():
+    # every caller stream gets a side stream of its own for the chunk
+    # transposes, up to 16 per device; calls on further streams run their
+    # chunks in order on the caller's stream.  Exactly 1024 spectra (the
+    # smallest chunked call) on 18 streams in flight at once, each equal to
+    # the result on the default stream.
+    X = xc()
+    n_in, P, ch0, n_ch = 2, 2, 640, 48
+    n_spec = 1024
+    say("fstage on many streams", n_in, n_spec)
+    adc, h = case(n_in, n_spec, P, seed=13)
+    gain = synth.fstage_gains(n_in, n_ch, h, seed=13).to(DEV)
+    hd = h.to(DEV)
+    ref = X.fstage(adc, hd, gain, ch0, n_ch)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(device=DEV) for _ in range(18)]
+    outs = []
+    for s in streams:
+        with torch.cuda.stream(s):
+            outs.append(X.fstage(adc, hd, gain, ch0, n_ch))
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        assert torch.equal(o, ref), k
+    # the first spectra against the oracle
+    a_np = adc.cpu().numpy()
+    hd64, gd = h.numpy().astype(np.float64), gain.cpu().numpy().astype(np.float64)
+    for m in (0, 1023):
+        frames = a_np[:, m * N:(m + P) * N]
+        v = oracle.fstage(frames, hd64, gd, N, P, ch0, n_ch, out="c128")
+        ok, _ = check_codes(ref[:, m:m + 1].cpu().numpy(), v, frame_bound(frames, h, P, float(np.abs(gd).max())))
+        assert ok.all(), m
