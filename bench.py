@@ -82,24 +82,56 @@ def time_path(torch, xcorr, x, w, path, steps, warmup, flags=0, per_step=None, c
     return ms, out, info
 
 
-def time_accumulate(torch, xcorr, x, w, steps, warmup):
+def time_accumulate(torch, xcorr, x, w, steps, warmup, per_step=None):
     """Average ms of xcorr_accumulate alone into an int64 plan: every window
     adds into the plan's int32 accumulator (read and written), which is
     folded into the int64 one before its sums could overflow (after
-    16777215 samples of 4-bit data, 65535 of 8-bit data)."""
+    16777215 samples of 4-bit data, 65535 of 8-bit data).  If per_step is a
+    list, the ms of each step are appended to it."""
     p = xcorr.Plan(w.n_inputs, w.n_channels, w.fmt, "i8")
     for _ in range(warmup):
         p.accumulate(x)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(p.stream)
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(p.stream)
+    for k in range(steps):
         p.accumulate(x)
-    e1.record(p.stream)
+        ev[k + 1].record(p.stream)
     torch.cuda.synchronize()
+    if per_step is not None:
+        per_step.extend(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
     p.close()
-    return e0.elapsed_time(e1) / steps
+    return ev[0].elapsed_time(ev[steps]) / steps
+
+
+def pcie_leg(torch, x, out_bytes, reps=3):
+    """Host-resident window: the input copied in from pinned host memory and
+    the int32 result copied back out (HIP events, best of `reps`), for the
+    PCIe-inclusive rate.  The boundary itself takes device buffers."""
+    dev = x.device
+    n_in = x.numel() * x.element_size()
+    flat = torch.empty(n_in, dtype=torch.uint8, device=dev)     # scratch: x itself stays intact
+    h_in = torch.empty(n_in, dtype=torch.uint8, pin_memory=True)
+    h_out = torch.empty(out_bytes, dtype=torch.uint8, pin_memory=True)
+    d_out = torch.empty(out_bytes, dtype=torch.uint8, device=dev)
+    s = torch.cuda.Stream(device=dev)
+    best_in = best_out = None
+    with torch.cuda.stream(s):
+        for _ in range(reps):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(s)
+            flat.copy_(h_in, non_blocking=True)
+            e1.record(s)
+            h_out.copy_(d_out, non_blocking=True)
+            e2.record(s)
+            s.synchronize()
+            t_in, t_out = e0.elapsed_time(e1), e1.elapsed_time(e2)
+            best_in = t_in if best_in is None else min(best_in, t_in)
+            best_out = t_out if best_out is None else min(best_out, t_out)
+    return {"h2d_bytes": flat.numel(), "h2d_ms": round(best_in, 3),
+            "h2d_gbs": round(flat.numel() / best_in / 1e6, 1),
+            "d2h_bytes": out_bytes, "d2h_ms": round(best_out, 3),
+            "d2h_gbs": round(out_bytes / best_out / 1e6, 1)}
 
 
 def percentile(v, q):
@@ -537,6 +569,7 @@ def main():
     ap.add_argument("--no-fstage", action="store_true", help="skip the F-stage leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the gating / tile-dump leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the PAPER-like and large-N windows")
+    ap.add_argument("--no-pcie", action="store_true", help="skip the host-transfer (PCIe) leg")
     ap.add_argument("--workload", default="lwa",
                     help="synthetic workload of the timed window (default lwa, the headline; others for profiling)")
     ap.add_argument("--tile", type=int, default=0,
@@ -615,7 +648,8 @@ def main():
     # the int32 accumulator's bound (4-bit: 2 * 8 * 8 per sample, 8-bit: 2 * 128 * 128)
     acc_bound = 16777215 if w.fmt == "ci4" else 65535
     acc_folds = acc_steps // max(1, acc_bound // w.n_time)
-    ms_acc = time_accumulate(torch, xcorr, x, w, acc_steps, 1)
+    acc_ms_steps = []
+    ms_acc = time_accumulate(torch, xcorr, x, w, acc_steps, 1, per_step=acc_ms_steps)
     log("int8, accumulate only (int64 accumulator): %.3f ms/window" % ms_acc)
 
     result = {
@@ -640,6 +674,9 @@ def main():
                             "pct_int8_peak": round(100 * 8 * cmac / (ms_acc * 1e-3) / 1e12 / PEAK_INT8_TOPS, 2),
                             "steps": acc_steps,
                             "folds_in_timed_steps": acc_folds,
+                            "step_ms": {"p10": round(percentile(acc_ms_steps, 10), 4),
+                                        "p50": round(percentile(acc_ms_steps, 50), 4),
+                                        "p90": round(percentile(acc_ms_steps, 90), 4)},
                             "note": "xcorr_accumulate of an int64 plan: int32 accumulator read and written per "
                                     "window, folded into the int64 one every %d samples" % acc_bound},
         "roofline": {"bound": "mfma",
@@ -663,6 +700,16 @@ def main():
     result["roofline"]["traffic"] = traffic
     result["roofline"]["traffic_source"] = how
     torch.cuda.empty_cache()
+    if not args.no_pcie:
+        log("host transfers of the same window (pinned memory)")
+        pc = pcie_leg(torch, x, out_bytes_i32)
+        t = pc["h2d_ms"] + ms + pc["d2h_ms"]
+        pc["pcie_inclusive_ms"] = round(t, 3)
+        pc["pcie_inclusive_tcmac_s"] = round(cmac / (t * 1e-3) / 1e12, 2)
+        pc["note"] = "input in from the host, the window, the int32 result out, one after another"
+        result["pcie"] = pc
+        log("pcie:", pc)
+        torch.cuda.empty_cache()
     if args.copy_calibration:
         copy_calibration(torch, xcorr, x, w)
 
