@@ -298,12 +298,70 @@ def serving_leg(torch, xcorr, seconds, speedups, seed=7, inflight=1):
     torch.cuda.synchronize()
     shapes = [(synth.subarray_workload(k, 1).n_inputs, synth.subarray_workload(k, 1).n_channels)
               for k in range(len(synth.SUBARRAYS))]
+    # one step of all five at 4096 samples: autotuned batch, graph replay,
+    # one launch per plan
+    step = batch_step(torch, xcorr, [pool[k][4096] for k in range(len(shapes))], shapes, autotune=True)
     tune = os.path.join(tempfile.mkdtemp(prefix="xcorr_tune_"), "tune.txt")
     runs = [run_serving(torch, xcorr, pool, shapes, seconds, sp, seed, tune, inflight) for sp in speedups]
     clean = [r["speedup_vs_real_time"] for r in runs if r["deadline_misses"] == 0]
     return {"workload": "5 subarrays of 16/48/96/200/352 dual-pol antennas, 512/1024/2048/256/128 channels, "
                         "4+4-bit, Poisson windows of 1024-4096 samples",
+            "step_4096_samples": step,
             "runs": runs, "largest_clean_speedup": max(clean) if clean else None}
+
+
+def batch_step(torch, xcorr, xs, shapes, autotune=False, reps=20):
+    """One integration step of several plans (window xs[k] for the plan of
+    shapes[k]) three ways: one batched launch per time chunk (optionally
+    with the autotuner's configuration), the same step captured once and
+    replayed as a graph, and one launch per plan.  Direct steps and replays
+    are each timed twice in turn after a warm-up (the clock settles over the
+    first tens of launches) and the better block of each is kept."""
+    dev = xs[0].device
+    s = torch.cuda.Stream(device=dev)        # a stream of their own: the step is also captured as a graph
+    plans = [xcorr.Plan(n_in, n_ch, "ci4", "i8", stream=s) for (n_in, n_ch) in shapes]
+    outs = [p.new_output() for p in plans]
+    b = xcorr.Batch(plans, stream=s)
+    torch.cuda.synchronize()
+    res = {}
+    if autotune:
+        cfg, _ = b.autotune(xs)
+        res["autotuned_config"] = cfg
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(step):
+        e0.record(s)
+        for _ in range(reps):
+            step()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    g = b.capture(xs, outs)
+    for _ in range(10):
+        b.run(xs, outs)
+        g.launch()
+    torch.cuda.synchronize()
+    run = lambda: b.run(xs, outs)
+    ms_batch, ms_graph = timed(run), timed(g.launch)
+    ms_batch, ms_graph = min(ms_batch, timed(run)), min(ms_graph, timed(g.launch))
+    g.close()
+
+    def per_plan():
+        for p, x, o in zip(plans, xs, outs):
+            p.accumulate_dump(x, o)
+    for _ in range(3):
+        per_plan()
+    torch.cuda.synchronize()
+    ms_seq = timed(per_plan)
+    b.close()
+    for p in plans:
+        p.close()
+    cmac = sum(n_in * (n_in + 1) // 2 * n_ch * x.shape[1] for (n_in, n_ch), x in zip(shapes, xs))
+    res.update({"one_batched_launch_ms": round(ms_batch, 4), "one_launch_per_plan_ms": round(ms_seq, 4),
+                "batched_speedup": round(ms_seq / ms_batch, 2), "one_graph_replay_ms": round(ms_graph, 4),
+                "tcmac_s_batched": round(cmac / ms_batch / 1e9, 2)})
+    return res
 
 
 def many_small_leg(torch, xcorr, seconds, speedups, n_sub=32, n_ant=16, n_ch=512, seed=9, inflight=1):
@@ -322,59 +380,12 @@ def many_small_leg(torch, xcorr, seconds, speedups, n_sub=32, n_ant=16, n_ch=512
         pool.append({t: synth.generate(synth.scaled(w, n_time=t), device=dev) for t in lens})
     torch.cuda.synchronize()
     xs = [pool[k][4096] for k in range(n_sub)]
-    s = torch.cuda.Stream(device=dev)        # a stream of their own: the step is also captured as a graph
-    plans = [xcorr.Plan(n_in, n_ch, "ci4", "i8", stream=s) for _ in range(n_sub)]
-    outs = [p.new_output() for p in plans]
-    b = xcorr.Batch(plans, stream=s)
-    torch.cuda.synchronize()
-    reps = 20
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def timed(step):
-        e0.record(b.stream)
-        for _ in range(reps):
-            step()
-        e1.record(b.stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
-
-    # the step launched directly and, captured once, replayed as a graph;
-    # each timed twice in turn after a warm-up (the clock settles over the
-    # first tens of launches), the better of each kept
-    g = b.capture(xs, outs)
-    for _ in range(10):
-        b.run(xs, outs)
-        g.launch()
-    torch.cuda.synchronize()
-    run = lambda: b.run(xs, outs)
-    ms_batch, ms_graph = timed(run), timed(g.launch)
-    ms_batch, ms_graph = min(ms_batch, timed(run)), min(ms_graph, timed(g.launch))
-    g.close()
-    stream = plans[0].stream
-    for _ in range(3):
-        for p, x, o in zip(plans, xs, outs):
-            p.accumulate_dump(x, o)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
-        for p, x, o in zip(plans, xs, outs):
-            p.accumulate_dump(x, o)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_seq = e0.elapsed_time(e1) / reps
-    b.close()
-    for p in plans:
-        p.close()
-    cmac = n_sub * n_in * (n_in + 1) // 2 * n_ch * 4096
+    step = batch_step(torch, xcorr, xs, [(n_in, n_ch)] * n_sub)
     runs = [run_serving(torch, xcorr, pool, [(n_in, n_ch)] * n_sub, seconds, sp, seed, inflight=inflight)
             for sp in speedups]
     clean = [r["speedup_vs_real_time"] for r in runs if r["deadline_misses"] == 0]
     return {"workload": "%d subarrays of %d dual-pol antennas, %d channels, 4+4-bit" % (n_sub, n_ant, n_ch),
-            "step_4096_samples": {"one_batched_launch_ms": round(ms_batch, 4),
-                                  "one_launch_per_plan_ms": round(ms_seq, 4),
-                                  "batched_speedup": round(ms_seq / ms_batch, 2),
-                                  "one_graph_replay_ms": round(ms_graph, 4),
-                                  "tcmac_s_batched": round(cmac / ms_batch / 1e9, 2)},
+            "step_4096_samples": step,
             "serving": runs, "largest_clean_speedup": max(clean) if clean else None}
 
 
