@@ -17,10 +17,11 @@
 // channels in registers for the whole run, and the next spectrum's samples
 // load while the current one is transformed.  Its 16 channels' codes go out
 // as one 16-byte store, input-major; a second, HBM-bound kernel transposes
-// them into X-stage order, chunk by chunk beside the next chunk's transform.  Twiddle factors are LDS tables built once per
-// workgroup in double precision.  fp32 arithmetic throughout; bound by VALU
-// work (about 36 flops per sample against 2.5 bytes of HBM traffic, the
-// transpose included).
+// them into X-stage order, chunk by chunk beside the next chunk's transform.
+// Twiddle factors are built once per workgroup in double precision (LDS
+// tables for the passes, registers for the real split).  fp32 arithmetic
+// throughout; bound by VALU work (about 36 flops per sample against 2.5
+// bytes of HBM traffic, the transpose included).
 #include "xcorr_fstage.h"
 
 #include <algorithm>
@@ -289,67 +290,67 @@ __global__ void __launch_bounds__(kThreads) fstage_transpose_kernel(FstageArgs a
     const int n_m = a.m_end - a.m_begin;
     const int n_tiles = n_ct * ((a.n_inputs + 127) / 128) * n_m;
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    int b = tile;
-    const int m = a.m_begin + b % n_m;  b /= n_m;
-    const int ct = b % n_ct;
-    const int at = b / n_ct;
-    const int cp0 = ct * 128, a0 = at * 128;
-    const int off = a.chan_begin - (a.chan_begin & ~15);
-    const uint8_t* w = (const uint8_t*)a.work;
+        int b = tile;
+        const int m = a.m_begin + b % n_m;  b /= n_m;
+        const int ct = b % n_ct;
+        const int at = b / n_ct;
+        const int cp0 = ct * 128, a0 = at * 128;
+        const int off = a.chan_begin - (a.chan_begin & ~15);
+        const uint8_t* w = (const uint8_t*)a.work;
 
-    {
-        // 16-byte loads: lane (c16, aq) reads channels cp0 + 16 c16 .. + 15
-        // of inputs a0 + 4 aq .. + 3; eight lanes cover a 128-byte row
-        const int c16 = t & 7, aq = t >> 3;
-        const int cp = cp0 + 16 * c16;
-        uint4 r[4];
+        {
+            // 16-byte loads: lane (c16, aq) reads channels cp0 + 16 c16 .. + 15
+            // of inputs a0 + 4 aq .. + 3; eight lanes cover a 128-byte row
+            const int c16 = t & 7, aq = t >> 3;
+            const int cp = cp0 + 16 * c16;
+            uint4 r[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int ar = a0 + 4 * aq + k;
-            r[k] = (ar < a.n_inputs && cp < a.cp)
-                       ? *(const uint4*)(w + ((int64_t)m * a.n_inputs + ar) * a.cp + cp) : make_uint4(0, 0, 0, 0);
-        }
-        const uint32_t* rr[4] = {&r[0].x, &r[1].x, &r[2].x, &r[3].x};
+            for (int k = 0; k < 4; ++k) {
+                const int ar = a0 + 4 * aq + k;
+                r[k] = (ar < a.n_inputs && cp < a.cp)
+                           ? *(const uint4*)(w + ((int64_t)m * a.n_inputs + ar) * a.cp + cp) : make_uint4(0, 0, 0, 0);
+            }
+            const uint32_t* rr[4] = {&r[0].x, &r[1].x, &r[2].x, &r[3].x};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            // 4 x 4 byte transpose of channels 4 j .. + 3: column cc holds
-            // the four inputs of channel 4 j + cc
-            const uint32_t r0 = rr[0][j], r1 = rr[1][j], r2 = rr[2][j], r3 = rr[3][j];
-            const uint32_t t0 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);
-            const uint32_t t1 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);
-            const uint32_t t2 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
-            const uint32_t t3 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
-            uint4 col;
-            col.x = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
-            col.y = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
-            col.z = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
-            col.w = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
-            *(uint4*)&T[aq][16 * c16 + 4 * j] = col;
-        }
-    }
-    __syncthreads();
-    {
-        // eight lanes write one channel's 128 inputs: full 128-byte rows
-        const int q = t & 7;                     // inputs a0 + 16 q .. + 15
-        const int ab = a0 + 16 * q;
-#pragma unroll
-        for (int pass = 0; pass < 4; ++pass) {
-            const int cl = 32 * pass + (t >> 3);
-            const int c = cp0 + cl - off;        // output channel
-            if (c < 0 || c >= a.n_chan || cp0 + cl >= a.cp || ab >= a.n_inputs) continue;
-            const uint4 d = make_uint4(T[4 * q][cl], T[4 * q + 1][cl], T[4 * q + 2][cl], T[4 * q + 3][cl]);
-            uint8_t* o = (uint8_t*)a.out + ((int64_t)c * a.n_spectra + m) * a.n_inputs + ab;
-            if (ab + 16 <= a.n_inputs && (a.n_inputs & 15) == 0) {
-                *(uint4*)o = d;
-            } else {
-                const uint32_t dw[4] = {d.x, d.y, d.z, d.w};
-#pragma unroll
-                for (int k = 0; k < 16; ++k)
-                    if (ab + k < a.n_inputs) o[k] = (uint8_t)(dw[k >> 2] >> (8 * (k & 3)));
+            for (int j = 0; j < 4; ++j) {
+                // 4 x 4 byte transpose of channels 4 j .. + 3: column cc holds
+                // the four inputs of channel 4 j + cc
+                const uint32_t r0 = rr[0][j], r1 = rr[1][j], r2 = rr[2][j], r3 = rr[3][j];
+                const uint32_t t0 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);
+                const uint32_t t1 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);
+                const uint32_t t2 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+                const uint32_t t3 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+                uint4 col;
+                col.x = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+                col.y = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+                col.z = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+                col.w = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+                *(uint4*)&T[aq][16 * c16 + 4 * j] = col;
             }
         }
-    }
-    __syncthreads();                             // T is refilled by the next tile
+        __syncthreads();
+        {
+            // eight lanes write one channel's 128 inputs: full 128-byte rows
+            const int q = t & 7;                     // inputs a0 + 16 q .. + 15
+            const int ab = a0 + 16 * q;
+#pragma unroll
+            for (int pass = 0; pass < 4; ++pass) {
+                const int cl = 32 * pass + (t >> 3);
+                const int c = cp0 + cl - off;        // output channel
+                if (c < 0 || c >= a.n_chan || cp0 + cl >= a.cp || ab >= a.n_inputs) continue;
+                const uint4 d = make_uint4(T[4 * q][cl], T[4 * q + 1][cl], T[4 * q + 2][cl], T[4 * q + 3][cl]);
+                uint8_t* o = (uint8_t*)a.out + ((int64_t)c * a.n_spectra + m) * a.n_inputs + ab;
+                if (ab + 16 <= a.n_inputs && (a.n_inputs & 15) == 0) {
+                    *(uint4*)o = d;
+                } else {
+                    const uint32_t dw[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+                    for (int k = 0; k < 16; ++k)
+                        if (ab + k < a.n_inputs) o[k] = (uint8_t)(dw[k >> 2] >> (8 * (k & 3)));
+                }
+            }
+        }
+        __syncthreads();                         // T is refilled by the next tile
     }
 }
 
