@@ -2,9 +2,13 @@
 //
 // Same tiling as the int8 kernel: per 16x16 block of complex outputs and
 // 32-sample step, four v_mfma_f32_16x16x32_f16:
-//   Re += A_a(I) B_a(J) + A_b(I) B_b(J)
-//   Im += A_b(I) B_a(J) + A_a(I) (-B_b(J))
-// fp16 negation is exact, so Im needs a single accumulator.  4- and 8-bit
+//   Re  += A_a(I) B_a(J) + A_b(I) B_b(J)
+//   -Im += A_a(I) B_b(J) + (-A_b(I)) B_a(J)
+// fp16 negation is exact, so Im needs a single accumulator; negating the
+// row block's operand (one per row block and step, not one per column
+// block) keeps the kernel within 256 registers, so that two workgroups
+// (80 KB of LDS each) share a CU and every SIMD runs two waves: one wave's
+// matrix work then covers the other's staging and barrier.  4- and 8-bit
 // integers are exact in fp16 and their products are exact in fp32; the fp32
 // sums are exact while every partial sum stays below 2^24.
 #include "xcorr_device.h"
@@ -154,7 +158,7 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJob& w, 
         if (KIND != KIND_NONE) {
             const uint8_t* pI = cur + si * kSlotBytes;
             const uint8_t* pJ = cur + sj * kSlotBytes;
-            v8h ia[4], ib[4], ja[4], jb[4], jbn[4];
+            v8h ia[4], ib[4], ja[4], jb[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 ia[b] = frag(pI, b, lane);
@@ -165,23 +169,23 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJob& w, 
                 if (KIND == KIND_DIAG) {
                     ja[b] = ia[b];
                     jb[b] = ib[b];
-                    jbn[b] = negate(ib[b]);
                 } else if (block_on(KIND, 3, b)) {
                     ja[b] = frag(pJ, b, lane);
                     jb[b] = frag(pJ + kPart, b, lane);
-                    jbn[b] = negate(jb[b]);
                 }
             }
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
+            for (int bi = 0; bi < 4; ++bi) {
+                const v8h ibn = negate(ib[bi]);
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj) {
                     if (!block_on(KIND, bi, bj)) continue;
                     acc_re[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ia[bi], ja[bj], acc_re[bi][bj], 0, 0, 0);
                     acc_re[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ib[bi], jb[bj], acc_re[bi][bj], 0, 0, 0);
-                    acc_im[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ib[bi], ja[bj], acc_im[bi][bj], 0, 0, 0);
-                    acc_im[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ia[bi], jbn[bj], acc_im[bi][bj], 0, 0, 0);
+                    acc_im[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ia[bi], jb[bj], acc_im[bi][bj], 0, 0, 0);
+                    acc_im[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ibn, ja[bj], acc_im[bi][bj], 0, 0, 0);
                 }
+            }
         }
         if (k + 1 < nk) st.store(lds + ((k + 1) & 1) * kBufBytes);
         __syncthreads();
@@ -204,7 +208,8 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJob& w, 
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + 16 * bi + 4 * (lane >> 4) + r;
                 if (i >= a.n_inputs || j > i) continue;
-                float re = acc_re[bi][bj][r], im = acc_im[bi][bj][r];
+                // acc_im holds -Im (0 - x also turns a -0 into +0)
+                float re = acc_re[bi][bj][r], im = 0.0f - acc_im[bi][bj][r];
                 const int64_t idx = ((int64_t)ch * nb + (int64_t)i * (i + 1) / 2 + j) * 2;
                 if (src) {
                     const float2 s = *(const float2*)(src + idx);
@@ -217,7 +222,7 @@ __device__ __forceinline__ void run_tile(const LaunchArgs& a, const WaveJob& w, 
 }
 
 template <int FMT>
-__global__ void __launch_bounds__(64 * kWavesF16, 1) xcorr_f16_kernel(LaunchArgs a)
+__global__ void __launch_bounds__(64 * kWavesF16, 2) xcorr_f16_kernel(LaunchArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
     const int b = work_item_index(blockIdx.x, a.n_blocks, a.xcd_map);
