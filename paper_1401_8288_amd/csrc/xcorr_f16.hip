@@ -20,6 +20,11 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 
+// LDS rows: the 64 bytes of a row's step as four 16-byte chunks, chunk c of
+// row r at position (c + r / 16) % 4 of an 80-byte row.  A 16-lane pass of
+// the fragment reads (16 consecutive rows, one chunk) and of the staging
+// writes (rows 4 apart for 4-bit samples, 2 apart for 8-bit ones, one
+// chunk) then falls on 16 different 16-byte bank groups of the 64 banks.
 constexpr int kStep = 32;                  // samples per LDS stage (64 bytes of fp16 per row)
 constexpr int kPitch = 80;
 constexpr int kPart = kRowBlock * kPitch;
@@ -61,7 +66,7 @@ struct Stager {
             if (FMT == 0) { col = 4 * (lane & 15); tc = lane >> 4; }
             else          { col = 2 * (lane & 31); tc = (lane >> 5) + 2 * j; }
             row[j] = col;
-            kofs[j] = 16 * tc;
+            kofs[j] = 16 * ((tc + (col >> 4)) & 3);   // chunk tc of rows col.. (same row / 16 for all of them)
             const int input = (w.stage_rb < 0 ? 0 : w.stage_rb) * kRowBlock + col;
             vofs[j] = (uint32_t)(8 * tc) * (uint32_t)a.row_bytes +
                       column_offset(input, a.n_inputs, FMT == 0 ? 1 : 2);
@@ -123,7 +128,7 @@ struct Stager {
 
 __device__ __forceinline__ v8h frag(const uint8_t* part, int blk, int lane)
 {
-    return *(const v8h*)(part + (16 * blk + (lane & 15)) * kPitch + 16 * (lane >> 4));
+    return *(const v8h*)(part + (16 * blk + (lane & 15)) * kPitch + 16 * (((lane >> 4) + blk) & 3));
 }
 
 __device__ __forceinline__ v8h negate(v8h x)
