@@ -21,10 +21,10 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // LDS rows: the 64 bytes of a row's step as four 16-byte chunks, chunk c of
-// row r at position (c + r / 16) % 4 of an 80-byte row.  A 16-lane pass of
-// the fragment reads (16 consecutive rows, one chunk) and of the staging
-// writes (rows 4 apart for 4-bit samples, 2 apart for 8-bit ones, one
-// chunk) then falls on 16 different 16-byte bank groups of the 64 banks.
+// row r at position (c + r / 16) % 4 of an 80-byte row.  Without the
+// rotation the staging writes of a wave (rows 4 apart for 4-bit samples, 2
+// apart for 8-bit ones, one chunk) fall on a quarter of the bank groups;
+// with it the counted bank-conflict cycles of the 4-bit window halve.
 constexpr int kStep = 32;                  // samples per LDS stage (64 bytes of fp16 per row)
 constexpr int kPitch = 80;
 constexpr int kPart = kRowBlock * kPitch;
